@@ -1,0 +1,226 @@
+"""Throughput of the PCV hot path on one MI355X.
+
+A step is one HMC transition of every fold x chain state: momentum refresh,
+S fused masked value/gradient evaluations with their leapfrog updates,
+Metropolis test, log predictive and online accumulation.  Inputs are resident
+in HBM before timing starts.
+
+Metric: gradient evaluations per second over all fold x chain states
+(C * S * steps / wall).  Default workload: blocked CV of a logistic GLM,
+n=100000, p=128, 10000 folds x 4 chains (40000 chains), S=8, bf16 hi+lo split
+MFMA contractions (BF16X3), synthetic data.
+
+Also reported on the same JSON line:
+  roofline      the gradient kernel's algorithmic flops per launch (4 n p C)
+                over its mean launch time from HIP events on the library's
+                stream during the timed region, against the dense bf16 peak;
+                HBM traffic from committed rocprofv3 counter summaries if any
+  cpu_baseline  the fp64 CPU oracle on a bounded sample of the same workload
+  plain_fp64    the unfused fp64 library path (DGEMM + materialised eta) on
+                the same workload, a few steps, and the speedup over it
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5]
+       [--precision bf16x3|bf16x5|fp64|fp32|fp64u] [--no-cpu-baseline]
+       [--no-plain-fp64] [--time-to-rhat]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2.5e15, "fp32": 157.3e12, "fp64": 78.6e12}
+PREC_NAMES = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x5": 3, "fp64u": 4}
+PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16", "bf16x5": "bf16", "fp64u": "f64"}
+PREC_PEAK = {"fp64": "fp64", "fp32": "fp32", "bf16x3": "bf16", "bf16x5": "bf16", "fp64u": "fp64"}
+DEFAULT_PREC = {"c1": "fp64", "c2": "fp32", "c3": "fp64", "c4": "bf16x3", "c5": "bf16x3"}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload_label(w, prec):
+    return (f"{w.name}: n={w.n} p={w.p} d={w.d} K={w.K} L={w.L} C={w.C} S={w.n_leapfrog} "
+            f"eps={w.step_size} precision={prec}")
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The oracle as it stands, on a bounded sample: the first folds of the
+    same workload (same chains, same random streams), as many transitions as
+    fit in the time budget."""
+    from oracle import sampler
+    from paper_2310_07002_amd import workloads as W
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads") or 0) for i in threadpool_info()) or None
+    except Exception:
+        pass
+    k_sub = max(1, min(w.K, 16 if w.n * w.p <= 1e6 else 4))
+    sub = W.fold_subset(w, 0, k_sub)
+    run = sampler.start(sub)
+    t0 = time.perf_counter()
+    iters = 0
+    while True:
+        sampler.advance(sub, run, 1)
+        iters += 1
+        if time.perf_counter() - t0 > budget_s or iters >= 500:
+            break
+    dt = time.perf_counter() - t0
+    rate = sub.C * sub.n_leapfrog * iters / dt
+    return {"value": rate, "unit": "gradient evals/s", "cores": threads or os.cpu_count(),
+            "kind": "oracle",
+            "sample": f"first {k_sub} folds ({sub.C} chains) of the same workload, {iters} transitions, "
+                      f"{dt:.1f} s, fp64 numpy"}
+
+
+def traffic_from_profiles(w, prec):
+    path = os.path.join(ROOT, "profiles", f"traffic_{w.name}_{prec}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        return t.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c5")
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain-fp64", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--time-to-rhat", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the path would shard whole folds across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_07002_amd import binding, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    prec = args.precision or DEFAULT_PREC[args.workload]
+    log(f"bench: generating workload {args.workload}")
+    w = W.make(args.workload)
+    stream = torch.cuda.current_stream()
+    log(f"bench: init {workload_label(w, prec)}")
+    s = binding.PCV.from_workload(w, precision=PREC_NAMES[prec], stream=stream)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    s.timing_read(reset=True)
+    s.timing_enable(True)
+    log(f"bench: timing {args.steps} transitions")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.timing_enable(False)
+    k_ms, k_n, k_name = s.timing_read(reset=True)
+    wall = t1 - t0
+    grads = w.C * w.n_leapfrog * args.steps
+    value = grads / wall
+    ms_per_step = wall / args.steps * 1e3
+    log(f"bench: {value:.4e} gradient evals/s, {ms_per_step:.3f} ms/transition, kernel {k_name}: "
+        f"{k_n} launches, {k_ms / max(k_n, 1):.4f} ms each")
+
+    # roofline of the gradient kernel
+    flops_per_launch = 4.0 * w.n * w.p * w.C
+    if prec in ("fp64", "fp32"):
+        # the fused transition kernel runs many transitions per launch
+        grads_per_launch = w.C * w.n_leapfrog * args.steps / max(k_n, 1)
+        flops_per_launch = 4.0 * w.n * w.p * grads_per_launch
+    avg_s = k_ms / max(k_n, 1) / 1e3
+    achieved = flops_per_launch / avg_s / 1e12 if avg_s > 0 else None
+    peak = PEAK[PREC_PEAK[prec]] / 1e12
+    roofline = {"bound": "mfma" if prec.startswith("bf16") else "alu",
+                "kernel": k_name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": (achieved / peak) if achieved else None,
+                "traffic": traffic_from_profiles(w, prec),
+                "alg_flops_per_launch": flops_per_launch, "mean_launch_ms": avg_s * 1e3,
+                "launches": k_n}
+    if prec.startswith("bf16"):
+        nprod = 6 if prec == "bf16x3" else 8
+        roofline["issued_mfma_frac"] = achieved * nprod / 4.0 / peak if achieved else None
+
+    line = {"metric": "gradient evals/sec over all fold×chain states", "value": value,
+            "unit": "gradient evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": PREC_DTYPE[prec], "precision_mode": prec,
+            "data": "synthetic (seeded; shaped like the paper's CV workloads, no datasets)",
+            "config": {"workload": workload_label(w, prec), "folds": w.K, "chains_per_fold": w.L,
+                       "chains": w.C, "leapfrog_steps": w.n_leapfrog, "parallelism": "single GPU"},
+            "roofline": roofline}
+
+    d = s.diagnostics() if args.warmup + args.steps > w.n_warmup + 1 else None
+    s.close()
+    del s
+
+    if not args.no_plain_fp64 and prec != "fp64u":
+        log("bench: plain fp64 path (library DGEMM, eta materialised)")
+        try:
+            b = binding.PCV.from_workload(w, precision=PREC_NAMES["fp64u"], stream=stream)
+            b.step(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.step(args.plain_steps)
+            torch.cuda.synchronize()
+            dtp = time.perf_counter() - t0
+            pv = w.C * w.n_leapfrog * args.plain_steps / dtp
+            line["plain_fp64"] = {"value": pv, "ms_per_step": dtp / args.plain_steps * 1e3,
+                                  "steps": args.plain_steps, "speedup": value / pv}
+            b.close()
+            del b
+        except Exception as e:  # report, never hide
+            line["plain_fp64"] = {"error": str(e)}
+
+    if args.time_to_rhat:
+        log("bench: full run for wall time to Rhat_max < 1.01")
+        r = binding.PCV.from_workload(w, precision=PREC_NAMES[prec], stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.step(w.n_warmup)
+        reached = None
+        done = 0
+        per_batch = w.batch_size
+        while done < w.n_samples:
+            r.step(per_batch)
+            done += per_batch
+            if done >= 2 * per_batch:
+                dd = r.diagnostics()
+                if dd["rhat_max"] < 1.01 and reached is None:
+                    reached = {"seconds": time.perf_counter() - t0, "draws": done, "elpd": dd["elpd"],
+                               "mcse": dd["mcse"], "rhat_max": dd["rhat_max"]}
+                    break
+        torch.cuda.synchronize()
+        dd = r.diagnostics()
+        line["time_to_rhat_max_1.01"] = reached or {"reached": False, "seconds": time.perf_counter() - t0,
+                                                    "final_rhat_max": dd["rhat_max"], "elpd": dd["elpd"],
+                                                    "mcse": dd["mcse"], "draws": dd["n_draws"]}
+        r.close()
+
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle, bounded sample)")
+        line["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * pcv.h -- C ABI of the MI355X (gfx950) library for parallel brute-force
+ * Bayesian cross-validation (PCV).
+ *
+ * Method: Cooper, Vehtari, Forbes, Simpson, Kennedy, "Bayesian
+ * cross-validation by parallel Markov chain Monte Carlo".  Every chain of
+ * every fold advances in lock-step with fixed-trajectory HMC (Section 3.3);
+ * each fold's log density and log predictive are masked sums over all rows
+ * (Appendix B); online accumulators give the LogS estimate, its Monte Carlo
+ * error, ESS and Rhat without storing draws (Algorithm A2, Appendix A).
+ *
+ * Conventions used by every entry point
+ *  - C = K * L chains; chain c belongs to fold k = c / L (its L chains are
+ *    adjacent).  Random streams are keyed by the global chain id
+ *    chain_offset + c, so a run over a subset of folds reproduces exactly the
+ *    same chains as the full run.
+ *  - d = p for the GLM families and p + 2 + n_groups for the hierarchical
+ *    logistic family (theta = [beta(p), mu, log tau, z(n_groups)]).
+ *  - Host arrays passed to pcv_init are copied; the caller may free them on
+ *    return.  Device pointers passed to the test hooks are borrowed for the
+ *    duration of the call and must be device memory of the current HIP device.
+ *  - All work is queued on the context's stream (pcv_set_stream); calls that
+ *    return host data synchronise that stream.
+ *  - Thread safety: a context must not be used from two threads at once.
+ *    Different contexts are independent.
+ *  - On error a call returns a non-zero pcv_status and leaves a message in
+ *    pcv_last_error(ctx).  After PCV_ERR_DEVICE the context only accepts
+ *    pcv_destroy.
+ */
+#ifndef PCV_H
+#define PCV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pcv_status {
+  PCV_OK = 0,
+  PCV_ERR_INVALID_ARG = 1,   /* bad sizes, non-finite data, invalid y, empty fold ... */
+  PCV_ERR_NOMEM = 2,         /* device or host allocation failed */
+  PCV_ERR_DEVICE = 3,        /* a HIP call or kernel launch failed */
+  PCV_ERR_STATE = 4,         /* not enough draws yet, or context unusable */
+  PCV_ERR_UNSUPPORTED = 5    /* combination of family / precision / size not built */
+} pcv_status;
+
+/* Likelihood families (Appendix B masks them per fold). */
+enum {
+  PCV_FAMILY_GAUSSIAN = 0,        /* y ~ N(x'theta, sigma^2), sigma known      */
+  PCV_FAMILY_LOGISTIC = 1,        /* y in {0,1}, logit link                   */
+  PCV_FAMILY_POISSON = 2,         /* y in {0,1,2,...}, log link               */
+  PCV_FAMILY_HIER_LOGISTIC = 3    /* logit(P(y=1)) = x'beta + mu + tau z_g(n) */
+};
+
+/* Arithmetic of the log-density / gradient contractions.  Metropolis
+ * energies, log predictive draws and all accumulators are fp64 always. */
+enum {
+  PCV_PREC_FP64 = 0,          /* fused fp64 VALU kernel (p <= 32)                   */
+  PCV_PREC_FP32 = 1,          /* fused fp32 VALU kernel (p <= 64)                   */
+  PCV_PREC_BF16X3 = 2,        /* bf16 MFMA, X and theta split hi+lo, 3 products each
+                                 way, fp32 accumulation (p = 64 or 128)             */
+  PCV_PREC_BF16X5 = 3,        /* as BF16X3 with a three-term theta split in the
+                                 forward product (5 products), fp32-exact eta        */
+  PCV_PREC_FP64_UNFUSED = 4   /* plain fp64 path: library DGEMMs with eta and the
+                                 residual materialised in memory (baseline)          */
+};
+
+/* Fold encodings.  Roles of a row in a fold: excluded, train or test. */
+enum {
+  PCV_FOLDS_INDEX = 0,      /* fold_index[n]: test in fold fold_index[n], train in
+                               every other fold; -1 = train in every fold           */
+  PCV_FOLDS_INTERVALS = 1,  /* intervals[K][4] = (test_lo, test_hi, excl_lo, excl_hi):
+                               [test_lo,test_hi) test, rest of [excl_lo,excl_hi)
+                               excluded, every other row train (hv-block, blocked) */
+  PCV_FOLDS_DENSE = 2       /* roles[K][n]: 0 excluded, 1 train, 2 test            */
+};
+
+typedef struct pcv_folds {
+  int32_t kind;
+  const int32_t* fold_index;   /* INDEX: n entries in [-1, K)                       */
+  const int64_t* intervals;    /* INTERVALS: K*4 entries, 0 <= lo <= hi <= n, excl ⊇ test */
+  const int8_t* roles;         /* DENSE: K*n entries in {0,1,2}                     */
+} pcv_folds;
+
+typedef struct pcv_model {
+  int32_t family;              /* PCV_FAMILY_*                                      */
+  int32_t precision;           /* PCV_PREC_*                                        */
+  int64_t n, p;                /* X is n x p, row-major, fp64                       */
+  int32_t K, L;                /* folds, chains per fold (L >= 2)                   */
+  int32_t n_groups;            /* HIER_LOGISTIC: number of groups                   */
+  const int32_t* group_of;     /* HIER_LOGISTIC: n entries in [0, n_groups), sorted */
+  double sigma;                /* GAUSSIAN: known noise sd                          */
+  const double* prior_scale;   /* d entries: theta_j ~ N(0, prior_scale_j^2) (GLMs);
+                                  NULL = all 1.  HIER: beta, mu, z ~ N(0,1),
+                                  tau ~ HalfNormal(1); the array is ignored          */
+  double step_size;            /* leapfrog step eps (> 0)                            */
+  int32_t n_leapfrog;          /* leapfrog steps per transition S (>= 1)             */
+  const double* inv_mass;      /* d entries (> 0): diagonal inverse mass matrix      */
+  const double* init_pos;      /* C*d, chain-major: theta of chain c at [c*d + j]   */
+  int64_t n_warmup;            /* transitions (cumulative over pcv_step) not accumulated */
+  int32_t batch_size;          /* b: draws per batch mean (>= 1)                     */
+  int32_t batches_per_block;   /* G: batches per shuffle block (>= 1)                */
+  int32_t n_blocks;            /* D: shuffle blocks (1..64); draws past D*G*b go
+                                  to the last block                                  */
+  uint64_t seed;               /* Philox4x32-10 key                                  */
+  int64_t chain_offset;        /* global id of chain 0 (0 for a full run)            */
+} pcv_model;
+
+typedef struct pcv_diag {
+  double rhat_max;        /* max over folds of Rhat (eq rhat-max); NaN if < 2 draws  */
+  double ess;             /* aggregate ESS of the elpd (Section 4.1); NaN if < 2 batches */
+  double elpd;            /* sum over folds of the LogS estimate                   */
+  double mcse;            /* Monte Carlo s.e. of elpd (eq mc-var)                  */
+  double accept_rate;     /* post-warm-up acceptance rate                          */
+  int64_t n_divergent;    /* post-warm-up divergent transitions                    */
+  int64_t n_draws;        /* post-warm-up draws per chain                          */
+  int64_t n_iter;         /* transitions run so far (warm-up included)             */
+  double* rhat_fold;      /* optional, K entries, caller-owned                      */
+  double* ess_fold;       /* optional, K entries, caller-owned                      */
+} pcv_diag;
+
+typedef struct pcv_ctx_s* pcv_ctx;
+
+/* Validate the model and data, copy them to the device, and evaluate log pi,
+ * its gradient and the log predictive at the initial positions (Section 3,
+ * Steps 2-3: every fold starts from draws of the full-data fit and reuses its
+ * step size and mass matrix, Section 3.1).
+ * X: n*p row-major fp64; y: n fp64.  Errors: PCV_ERR_INVALID_ARG (n, p, K <= 0;
+ * L < 2; non-finite X, y or init_pos; y outside the family's support; a fold
+ * with no test or no training row; step_size, inv_mass, sigma <= 0;
+ * n_leapfrog < 1; batch settings < 1), PCV_ERR_UNSUPPORTED, PCV_ERR_NOMEM,
+ * PCV_ERR_DEVICE.  *out is NULL on error. */
+pcv_status pcv_init(pcv_ctx* out, const pcv_model* model, const double* X, const double* y,
+                    const pcv_folds* fold_masks);
+
+/* Queue all further work of ctx on hip_stream (a hipStream_t; NULL = the
+ * default stream).  The stream must outlive its use by ctx. */
+pcv_status pcv_set_stream(pcv_ctx ctx, void* hip_stream);
+
+/* Advance every chain n_iter HMC transitions (n_iter >= 0).  The first
+ * model->n_warmup transitions overall are warm-up and are not accumulated.
+ * Asynchronous on the context stream.  Divergent transitions are counted,
+ * not errors. */
+pcv_status pcv_step(pcv_ctx ctx, int64_t n_iter);
+
+/* Convergence diagnostics of the LogS estimate (Section 4) from the online
+ * accumulators.  Synchronises.  Returns PCV_ERR_STATE if fewer than 2
+ * post-warm-up draws exist; values that need complete batches are NaN until
+ * 2 batches are complete. */
+pcv_status pcv_diagnostics(pcv_ctx ctx, pcv_diag* out);
+
+/* LogS cross-validation estimate (eq cv-score) and its Monte Carlo standard
+ * error (eq mc-var), in total and per fold (K entries each, optional).
+ * Synchronises.  PCV_ERR_STATE if there is no post-warm-up draw. */
+pcv_status pcv_elpd(pcv_ctx ctx, double* elpd, double* mcse, double* elpd_fold, double* mcse_fold);
+
+/* Block-shuffle benchmark of Rhat_max (Section 4.2, Fig. 4; last loop of
+ * Algorithm A2): R replicates, each rebuilding every chain from D blocks
+ * drawn with replacement from the fold's chains (Philox stream of `seed`).
+ * rhat_max_rep: R entries (caller-owned).  rhat_rep: K*R entries or NULL.
+ * Synchronises.  PCV_ERR_STATE before 2 draws, PCV_ERR_INVALID_ARG if R < 1. */
+pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* rhat_max_rep,
+                                 double* rhat_rep);
+
+void pcv_destroy(pcv_ctx ctx);
+const char* pcv_last_error(pcv_ctx ctx);
+const char* pcv_status_str(pcv_status s);
+
+/* ---- lower-level calls (gradient checks, parity tests, state transfer) ---- */
+
+/* Masked log density log pi (Appendix B) and, if want_grad, its gradient
+ * (the hand-written adjoint), for caller-given positions.  theta_dev: C*d
+ * chain-major fp64 device array; logp_dev: C fp64; grad_dev: C*d fp64 or NULL
+ * when want_grad = 0.  Uses the context's precision.  Does not change the
+ * chain state. */
+pcv_status pcv_logdensity_grad(pcv_ctx ctx, const double* theta_dev, double* logp_dev,
+                               double* grad_dev, int32_t want_grad);
+
+/* n_steps leapfrog steps (step size of the model) from (q, p) for every
+ * chain, as inside one HMC transition.  All arrays are C*d (logp: C) fp64
+ * device arrays, chain-major.  Does not change the chain state. */
+pcv_status pcv_leapfrog(pcv_ctx ctx, const double* q_dev, const double* p_dev, int32_t n_steps,
+                        double* q_out_dev, double* p_out_dev, double* logp_out_dev,
+                        double* grad_out_dev);
+
+/* Copy the current chain state to host buffers (any may be NULL):
+ * theta C*d chain-major, logp C, log predictive s C. Synchronises. */
+pcv_status pcv_get_state(pcv_ctx ctx, double* theta, double* logp, double* s);
+
+/* Replace the chain positions (C*d chain-major host array) and recompute
+ * log pi, its gradient and s there.  Accumulators are kept. */
+pcv_status pcv_set_state(pcv_ctx ctx, const double* theta);
+
+/* Raw online accumulators (Algorithm A2) to host buffers, any may be NULL:
+ * Z, U, U2, V, V2: C each (log scale); blk_mean, blk_m2: D*C each
+ * (block-major: [dd*C + c]); n_accept, n_divergent: C each. */
+pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, double* V,
+                                double* V2, double* blk_mean, double* blk_m2,
+                                int64_t* n_accept, int64_t* n_divergent);
+
+/* Philox4x32-10 of this library for n counters (c0, c1, c2, c3 + i) with key
+ * (seed): out receives 4*n uint32 words.  Host-side buffers; runs on the
+ * device.  Used to check the stream bit-for-bit against other implementations. */
+pcv_status pcv_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                      int64_t n, uint32_t* out);
+
+/* Per-launch timing of the gradient kernel (the S-fold hot kernel of every
+ * transition).  When enabled, every launch of it queued by pcv_step is
+ * bracketed by HIP events on the context stream.  pcv_timing_read
+ * synchronises, returns the summed device milliseconds and the number of
+ * launches since the last reset, and the kernel's name (static string), and
+ * resets the counters if reset != 0. */
+pcv_status pcv_timing_enable(pcv_ctx ctx, int32_t on);
+pcv_status pcv_timing_read(pcv_ctx ctx, double* ms_sum, int64_t* n_launches,
+                           const char** kernel_name, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCV_H */

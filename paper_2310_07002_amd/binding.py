@@ -1,0 +1,306 @@
+"""ctypes binding of libpcv.so (include/pcv.h), same names as the C ABI.
+
+Argument marshalling only: every step of the sampler runs in the library's
+HIP kernels.  Device arrays for the lower-level calls are torch tensors on the
+current HIP device; host arrays are numpy arrays.  The library is loaded from
+this package directory; importing works without a GPU, but calls that touch
+the device fail loudly if there is none.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcv.so")
+
+PCV_OK = 0
+STATUS_NAMES = {0: "PCV_OK", 1: "PCV_ERR_INVALID_ARG", 2: "PCV_ERR_NOMEM", 3: "PCV_ERR_DEVICE",
+                4: "PCV_ERR_STATE", 5: "PCV_ERR_UNSUPPORTED"}
+
+EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_elpd",
+            "pcv_shuffle_benchmark", "pcv_destroy", "pcv_last_error", "pcv_status_str",
+            "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
+            "pcv_get_accumulators", "pcv_philox", "pcv_timing_enable", "pcv_timing_read"]
+
+
+class PcvError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class pcv_folds(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32),
+                ("fold_index", ctypes.POINTER(ctypes.c_int32)),
+                ("intervals", ctypes.POINTER(ctypes.c_int64)),
+                ("roles", ctypes.POINTER(ctypes.c_int8))]
+
+
+class pcv_model(ctypes.Structure):
+    _fields_ = [("family", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("K", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("n_groups", ctypes.c_int32), ("group_of", ctypes.POINTER(ctypes.c_int32)),
+                ("sigma", ctypes.c_double), ("prior_scale", ctypes.POINTER(ctypes.c_double)),
+                ("step_size", ctypes.c_double), ("n_leapfrog", ctypes.c_int32),
+                ("inv_mass", ctypes.POINTER(ctypes.c_double)),
+                ("init_pos", ctypes.POINTER(ctypes.c_double)),
+                ("n_warmup", ctypes.c_int64), ("batch_size", ctypes.c_int32),
+                ("batches_per_block", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64)]
+
+
+class pcv_diag(ctypes.Structure):
+    _fields_ = [("rhat_max", ctypes.c_double), ("ess", ctypes.c_double),
+                ("elpd", ctypes.c_double), ("mcse", ctypes.c_double),
+                ("accept_rate", ctypes.c_double), ("n_divergent", ctypes.c_int64),
+                ("n_draws", ctypes.c_int64), ("n_iter", ctypes.c_int64),
+                ("rhat_fold", ctypes.POINTER(ctypes.c_double)),
+                ("ess_fold", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libpcv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2310_07002_amd.build")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, U64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "pcv_init": ([ctypes.POINTER(P), ctypes.POINTER(pcv_model), dp, dp, ctypes.POINTER(pcv_folds)], I32),
+        "pcv_set_stream": ([P, P], I32),
+        "pcv_step": ([P, I64], I32),
+        "pcv_diagnostics": ([P, ctypes.POINTER(pcv_diag)], I32),
+        "pcv_elpd": ([P, dp, dp, dp, dp], I32),
+        "pcv_shuffle_benchmark": ([P, I32, U64, dp, dp], I32),
+        "pcv_destroy": ([P], None),
+        "pcv_last_error": ([P], ctypes.c_char_p),
+        "pcv_status_str": ([I32], ctypes.c_char_p),
+        "pcv_logdensity_grad": ([P, P, P, P, I32], I32),
+        "pcv_leapfrog": ([P, P, P, I32, P, P, P, P], I32),
+        "pcv_get_state": ([P, dp, dp, dp], I32),
+        "pcv_set_state": ([P, dp], I32),
+        "pcv_get_accumulators": ([P, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
+        "pcv_philox": ([U64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, I64,
+                        ctypes.POINTER(ctypes.c_uint32)], I32),
+        "pcv_timing_enable": ([P, I32], I32),
+        "pcv_timing_read": ([P, dp, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_char_p), I32], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _dev(t) -> ctypes.c_void_p:
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != __import__("torch").float64 or not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous float64 tensors on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def pcv_philox(seed: int, c0: int, c1: int, c2: int, c3: int, n: int) -> np.ndarray:
+    lib = load_library()
+    out = np.zeros(4 * n, dtype=np.uint32)
+    st = lib.pcv_philox(seed, c0, c1, c2, c3, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    if st != PCV_OK:
+        raise PcvError(st, "pcv_philox failed")
+    return out.reshape(n, 4)
+
+
+class PCV:
+    """One sampler context (pcv_ctx).  Thin wrapper; see include/pcv.h."""
+
+    def __init__(self, *, family: int, precision: int, X: np.ndarray, y: np.ndarray, K: int, L: int,
+                 fold_kind: int, fold_index=None, intervals=None, roles=None, group_of=None,
+                 n_groups: int = 0, sigma: float = 1.0, prior_scale=None, step_size: float,
+                 n_leapfrog: int, inv_mass, init_pos, n_warmup: int, batch_size: int,
+                 batches_per_block: int, n_blocks: int, seed: int, chain_offset: int = 0,
+                 stream=None):
+        self._lib = load_library()
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        n, p = X.shape
+        self.n, self.p, self.K, self.L = n, p, int(K), int(L)
+        self.C = self.K * self.L
+        self.d = p + 2 + n_groups if group_of is not None else p
+        keep = []
+
+        def arr(a, dt):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a
+
+        inv_mass = arr(inv_mass, np.float64)
+        init_pos = arr(init_pos, np.float64)
+        prior_scale = arr(prior_scale, np.float64)
+        go = arr(group_of, np.int32)
+        fi = arr(fold_index, np.int32)
+        iv = arr(intervals, np.int64)
+        rl = arr(roles, np.int8)
+        m = pcv_model()
+        m.family, m.precision = family, precision
+        m.n, m.p, m.K, m.L = n, p, K, L
+        m.n_groups = n_groups
+        m.group_of = go.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if go is not None else None
+        m.sigma = sigma
+        m.prior_scale = _dptr(prior_scale)
+        m.step_size, m.n_leapfrog = step_size, n_leapfrog
+        m.inv_mass = _dptr(inv_mass)
+        m.init_pos = _dptr(init_pos)
+        m.n_warmup, m.batch_size = n_warmup, batch_size
+        m.batches_per_block, m.n_blocks = batches_per_block, n_blocks
+        m.seed, m.chain_offset = seed, chain_offset
+        f = pcv_folds()
+        f.kind = fold_kind
+        f.fold_index = fi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if fi is not None else None
+        f.intervals = iv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if iv is not None else None
+        f.roles = rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)) if rl is not None else None
+        self._ctx = ctypes.c_void_p()
+        st = self._lib.pcv_init(ctypes.byref(self._ctx), ctypes.byref(m), _dptr(X), _dptr(y), ctypes.byref(f))
+        if st != PCV_OK:
+            self._ctx = None
+            raise PcvError(st, "pcv_init failed (details on stderr)")
+        if stream is not None:
+            self.set_stream(stream)
+
+    @classmethod
+    def from_workload(cls, w, precision: Optional[int] = None, stream=None) -> "PCV":
+        return cls(family=w.family, precision=w.precision if precision is None else precision,
+                   X=w.X, y=w.y, K=w.K, L=w.L, fold_kind=w.fold_kind, fold_index=w.fold_index,
+                   intervals=w.intervals, roles=w.roles, group_of=w.group_of, n_groups=w.n_groups,
+                   sigma=w.sigma, prior_scale=w.prior_scale, step_size=w.step_size,
+                   n_leapfrog=w.n_leapfrog, inv_mass=w.inv_mass, init_pos=w.init_pos,
+                   n_warmup=w.n_warmup, batch_size=w.batch_size,
+                   batches_per_block=w.batches_per_block, n_blocks=w.n_blocks, seed=w.seed,
+                   chain_offset=w.chain_offset, stream=stream)
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, st: int, what: str):
+        if st != PCV_OK:
+            msg = self._lib.pcv_last_error(self._ctx)
+            raise PcvError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.pcv_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C ABI -----------------------------------------------------------------
+    def set_stream(self, stream):
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self._check(self._lib.pcv_set_stream(self._ctx, ctypes.c_void_p(handle)), "pcv_set_stream")
+
+    def step(self, n_iter: int):
+        self._check(self._lib.pcv_step(self._ctx, int(n_iter)), "pcv_step")
+
+    def diagnostics(self) -> dict:
+        rf = np.zeros(self.K)
+        ef = np.zeros(self.K)
+        d = pcv_diag()
+        d.rhat_fold = _dptr(rf)
+        d.ess_fold = _dptr(ef)
+        self._check(self._lib.pcv_diagnostics(self._ctx, ctypes.byref(d)), "pcv_diagnostics")
+        return {"rhat_max": d.rhat_max, "ess": d.ess, "elpd": d.elpd, "mcse": d.mcse,
+                "accept_rate": d.accept_rate, "n_divergent": d.n_divergent, "n_draws": d.n_draws,
+                "n_iter": d.n_iter, "rhat_fold": rf, "ess_fold": ef}
+
+    def elpd(self) -> dict:
+        e = ctypes.c_double()
+        s = ctypes.c_double()
+        ef = np.zeros(self.K)
+        sf = np.zeros(self.K)
+        self._check(self._lib.pcv_elpd(self._ctx, ctypes.byref(e), ctypes.byref(s), _dptr(ef), _dptr(sf)),
+                    "pcv_elpd")
+        return {"elpd": e.value, "mcse": s.value, "elpd_fold": ef, "mcse_fold": sf}
+
+    def shuffle_benchmark(self, R: int, seed: int, per_fold: bool = False):
+        mx = np.zeros(R)
+        rep = np.zeros(self.K * R) if per_fold else None
+        self._check(self._lib.pcv_shuffle_benchmark(self._ctx, R, seed, _dptr(mx), _dptr(rep)),
+                    "pcv_shuffle_benchmark")
+        return (mx, rep.reshape(self.K, R)) if per_fold else mx
+
+    def logdensity_grad(self, theta, want_grad: bool = True):
+        """theta: [C, d] float64 cuda tensor -> (logp [C], grad [C, d] or None)."""
+        import torch
+        logp = torch.empty(self.C, dtype=torch.float64, device=theta.device)
+        grad = torch.empty_like(theta) if want_grad else None
+        self._check(self._lib.pcv_logdensity_grad(self._ctx, _dev(theta), _dev(logp), _dev(grad),
+                                                  1 if want_grad else 0), "pcv_logdensity_grad")
+        return logp, grad
+
+    def leapfrog(self, q, p, n_steps: int):
+        import torch
+        q_out = torch.empty_like(q)
+        p_out = torch.empty_like(p)
+        logp = torch.empty(self.C, dtype=torch.float64, device=q.device)
+        grad = torch.empty_like(q)
+        self._check(self._lib.pcv_leapfrog(self._ctx, _dev(q), _dev(p), int(n_steps), _dev(q_out),
+                                           _dev(p_out), _dev(logp), _dev(grad)), "pcv_leapfrog")
+        return q_out, p_out, logp, grad
+
+    def get_state(self):
+        th = np.zeros((self.C, self.d))
+        lp = np.zeros(self.C)
+        s = np.zeros(self.C)
+        self._check(self._lib.pcv_get_state(self._ctx, _dptr(th), _dptr(lp), _dptr(s)), "pcv_get_state")
+        return th, lp, s
+
+    def set_state(self, theta: np.ndarray):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        self._check(self._lib.pcv_set_state(self._ctx, _dptr(th)), "pcv_set_state")
+
+    def get_accumulators(self, n_blocks: int) -> dict:
+        C = self.C
+        out = {k: np.zeros(C) for k in ("Z", "U", "U2", "V", "V2")}
+        out["blk_mean"] = np.zeros(n_blocks * C)
+        out["blk_m2"] = np.zeros(n_blocks * C)
+        out["n_accept"] = np.zeros(C, dtype=np.int64)
+        out["n_divergent"] = np.zeros(C, dtype=np.int64)
+        i64 = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        self._check(self._lib.pcv_get_accumulators(
+            self._ctx, _dptr(out["Z"]), _dptr(out["U"]), _dptr(out["U2"]), _dptr(out["V"]),
+            _dptr(out["V2"]), _dptr(out["blk_mean"]), _dptr(out["blk_m2"]), i64(out["n_accept"]),
+            i64(out["n_divergent"])), "pcv_get_accumulators")
+        out["blk_mean"] = out["blk_mean"].reshape(n_blocks, C).T.copy()
+        out["blk_m2"] = out["blk_m2"].reshape(n_blocks, C).T.copy()
+        return out
+
+    def timing_enable(self, on: bool = True):
+        self._check(self._lib.pcv_timing_enable(self._ctx, 1 if on else 0), "pcv_timing_enable")
+
+    def timing_read(self, reset: bool = True):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        name = ctypes.c_char_p()
+        self._check(self._lib.pcv_timing_read(self._ctx, ctypes.byref(ms), ctypes.byref(n),
+                                              ctypes.byref(name), 1 if reset else 0), "pcv_timing_read")
+        return ms.value, n.value, name.value.decode()

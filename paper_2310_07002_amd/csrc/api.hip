@@ -1,0 +1,845 @@
+// Host runtime of the PCV library: validation, device buffers, path
+// selection, transition scheduling and the C ABI declared in include/pcv.h.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pcv_internal.h"
+
+namespace pcv {
+// launchers (k_valu.hip, k_mfma.hip, k_common.hip)
+hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int mode, int64_t t0,
+                       int n_iter, int n_steps, hipStream_t st);
+size_t valu_smem_bytes(bool fp64, int W, int family, int n_groups);
+int valu_pb(int64_t p, bool fp64);
+hipError_t launch_mfma(const DevModel& m, const uint4* Xpk, const float* ty, const int32_t* tfid, float* Gpart,
+                       double* Vpart, int n_tiles, int tiles_per_split, int n_splits, int fwd, bool value,
+                       hipStream_t st);
+hipError_t launch_mfma_pack(const double* X, int64_t n, int P, int n_tiles, uint4* out, hipStream_t st);
+int mfma_chain_tile();
+int mfma_rows_per_tile();
+int mfma_nfrag(int P);
+hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st);
+hipError_t launch_reduce_f32(const DevModel& m, const float* G, int ns, int mode, hipStream_t st);
+hipError_t launch_reduce_f64(const DevModel& m, const double* G, int ns, int mode, hipStream_t st);
+hipError_t launch_value_finish(const DevModel& m, const double* V, int ns, hipStream_t st);
+hipError_t launch_accept(const DevModel& m, const double* V, int ns, int64_t t, hipStream_t st);
+hipError_t launch_logpred(const DevModel& m, hipStream_t st);
+hipError_t launch_unfused_resid(const DevModel& m, double* eta, int64_t c0, int64_t cc, double* V, int want_value,
+                                hipStream_t st);
+hipError_t launch_rowconst(const DevModel& m, double* rowc, hipStream_t st);
+hipError_t launch_foldconst(const DevModel& m, double prior_const, double* fc, hipStream_t st);
+hipError_t launch_to_dc(const double* src, double* dst, int64_t C, int64_t d, hipStream_t st);
+hipError_t launch_to_cd(const double* src, double* dst, int64_t C, int64_t d, hipStream_t st);
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st);
+hipError_t launch_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                         uint32_t* out, hipStream_t st);
+hipError_t launch_diag(const DevModel& m, int64_t N, double* fold_buf, double* out, hipStream_t st);
+hipError_t launch_shuffle(const DevModel& m, int64_t N, int R, uint32_t s0, uint32_t s1, double* rep,
+                          double* repmax, hipStream_t st);
+hipError_t launch_kick_drift(const DevModel& m, hipStream_t st);
+}  // namespace pcv
+
+using namespace pcv;
+
+enum Path { PATH_VALU = 0, PATH_MFMA = 1, PATH_UNFUSED = 2 };
+
+struct pcv_ctx_s {
+  DevModel m{};
+  int prec = 0, path = 0;
+  bool fp64 = true;
+  int pb = 0, W = 1;
+  hipStream_t st = nullptr;
+  int64_t t = 0;
+  std::vector<void*> allocs;
+  // VALU
+  void* Xv = nullptr;
+  int32_t* wave_rows = nullptr;
+  // MFMA
+  uint4* Xpk = nullptr;
+  float* ty = nullptr;
+  int32_t* tfid = nullptr;
+  float* Gpart = nullptr;
+  double* Vpart = nullptr;
+  int n_tiles = 0, tiles_per_split = 0, n_splits = 1, fwd = 3;
+  // unfused
+  rocblas_handle rb = nullptr;
+  double* eta = nullptr;
+  double* Gpart64 = nullptr;
+  int64_t chunk = 0;
+  // diagnostics
+  double* fold_buf = nullptr;
+  double* dscal = nullptr;
+  double prior_const = 0.0;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  double ms_acc = 0.0;
+  int64_t n_launch = 0;
+  std::string err;
+  bool dead = false;
+};
+
+namespace {
+
+const char* kGradKernelName[3] = {"k_valu (fused transition)", "k_mfma (bf16 split MFMA value+gradient)",
+                                  "rocblas_dgemm + k_unfused_resid (fp64 unfused)"};
+
+pcv_status fail(pcv_ctx ctx, pcv_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+#define CK(call)                                                                                   \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
+    if (e_ != hipSuccess) {                                                                        \
+      ctx->dead = true;                                                                            \
+      return fail(ctx, PCV_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));        \
+    }                                                                                              \
+  } while (0)
+
+template <typename T>
+pcv_status dalloc(pcv_ctx ctx, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, PCV_ERR_NOMEM, "hipMalloc failed");
+  }
+  ctx->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return PCV_OK;
+}
+
+#define TRY(x)                       \
+  do {                               \
+    pcv_status s_ = (x);             \
+    if (s_ != PCV_OK) return s_;     \
+  } while (0)
+
+template <typename T>
+pcv_status upload(pcv_ctx ctx, T** dst, const T* src, size_t count) {
+  TRY(dalloc(ctx, dst, count));
+  CK(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return PCV_OK;
+}
+
+bool usable(pcv_ctx ctx) { return ctx && !ctx->dead; }
+
+void timing_begin(pcv_ctx ctx) {
+  if (!ctx->timing) return;
+  while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    ctx->ev_pool.push_back(e);
+  }
+  (void)hipEventRecord(ctx->ev_pool[ctx->ev_used], ctx->st);
+}
+void timing_end(pcv_ctx ctx) {
+  if (!ctx->timing || ctx->ev_pool.size() < ctx->ev_used + 2) return;
+  (void)hipEventRecord(ctx->ev_pool[ctx->ev_used + 1], ctx->st);
+  ctx->ev_used += 2;
+  ctx->n_launch += 1;
+}
+void timing_collect(pcv_ctx ctx) {
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(ctx->ev_pool[i + 1]);
+    if (hipEventElapsedTime(&ms, ctx->ev_pool[i], ctx->ev_pool[i + 1]) == hipSuccess) ctx->ms_acc += ms;
+  }
+  ctx->ev_used = 0;
+}
+
+// Partial gradient (and value) at q1 for the split paths.
+pcv_status split_partials(pcv_ctx ctx, bool value) {
+  DevModel& m = ctx->m;
+  if (ctx->path == PATH_MFMA) {
+    if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
+    timing_begin(ctx);
+    CK(launch_mfma(m, ctx->Xpk, ctx->ty, ctx->tfid, ctx->Gpart, ctx->Vpart, ctx->n_tiles, ctx->tiles_per_split,
+                   ctx->n_splits, ctx->fwd, value, ctx->st));
+    timing_end(ctx);
+    return PCV_OK;
+  }
+  // unfused fp64: eta = X Theta (library GEMM), residual, G' = R' X (library GEMM)
+  if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
+  timing_begin(ctx);
+  const double one = 1.0, zero = 0.0;
+  for (int64_t c0 = 0; c0 < m.C; c0 += ctx->chunk) {
+    const int64_t cc = std::min<int64_t>(ctx->chunk, m.C - c0);
+    if (rocblas_dgemm(ctx->rb, rocblas_operation_transpose, rocblas_operation_transpose, (rocblas_int)m.n,
+                      (rocblas_int)cc, (rocblas_int)m.p, &one, m.X64, (rocblas_int)m.p, m.q1 + c0,
+                      (rocblas_int)m.C, &zero, ctx->eta, (rocblas_int)m.n) != rocblas_status_success)
+      return fail(ctx, PCV_ERR_DEVICE, "rocblas_dgemm (eta) failed");
+    CK(launch_unfused_resid(m, ctx->eta, c0, cc, ctx->Vpart, value ? 1 : 0, ctx->st));
+    if (rocblas_dgemm(ctx->rb, rocblas_operation_transpose, rocblas_operation_transpose, (rocblas_int)cc,
+                      (rocblas_int)m.p, (rocblas_int)m.n, &one, ctx->eta, (rocblas_int)m.n, m.X64,
+                      (rocblas_int)m.p, &zero, ctx->Gpart64 + c0, (rocblas_int)m.C) != rocblas_status_success)
+      return fail(ctx, PCV_ERR_DEVICE, "rocblas_dgemm (gradient) failed");
+  }
+  timing_end(ctx);
+  return PCV_OK;
+}
+
+pcv_status split_reduce(pcv_ctx ctx, int mode) {
+  if (ctx->path == PATH_MFMA) CK(launch_reduce_f32(ctx->m, ctx->Gpart, ctx->n_splits, mode, ctx->st));
+  else CK(launch_reduce_f64(ctx->m, ctx->Gpart64, 1, mode, ctx->st));
+  return PCV_OK;
+}
+
+int split_count(pcv_ctx ctx) { return ctx->path == PATH_MFMA ? ctx->n_splits : 1; }
+
+// Value and gradient at q1 into logp1 / g1 (no leapfrog update).
+pcv_status eval_q1(pcv_ctx ctx) {
+  if (ctx->path == PATH_VALU) {
+    CK(launch_valu(ctx->m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, 1, 0, 0, 0, ctx->st));
+    return PCV_OK;
+  }
+  TRY(split_partials(ctx, true));
+  TRY(split_reduce(ctx, 0));
+  CK(launch_value_finish(ctx->m, ctx->Vpart, split_count(ctx), ctx->st));
+  return PCV_OK;
+}
+
+// q0 := q1 state after eval_q1, plus s0.
+pcv_status adopt_q1(pcv_ctx ctx) {
+  DevModel& m = ctx->m;
+  const size_t bytes = sizeof(double) * m.d * m.C;
+  CK(hipMemcpyAsync(m.q0, m.q1, bytes, hipMemcpyDeviceToDevice, ctx->st));
+  CK(hipMemcpyAsync(m.g0, m.g1, bytes, hipMemcpyDeviceToDevice, ctx->st));
+  CK(hipMemcpyAsync(m.logp0, m.logp1, sizeof(double) * m.C, hipMemcpyDeviceToDevice, ctx->st));
+  CK(launch_logpred(m, ctx->st));
+  return PCV_OK;
+}
+
+pcv_status transition_split(pcv_ctx ctx, int64_t t) {
+  DevModel& m = ctx->m;
+  CK(launch_momentum(m, t, ctx->st));
+  for (int s = 0; s < m.S; ++s) {
+    const bool last = s == m.S - 1;
+    TRY(split_partials(ctx, last));
+    TRY(split_reduce(ctx, last ? 2 : 1));
+  }
+  CK(launch_accept(m, ctx->Vpart, split_count(ctx), t, ctx->st));
+  return PCV_OK;
+}
+
+bool finite_all(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pcv_status_str(pcv_status s) {
+  switch (s) {
+    case PCV_OK: return "ok";
+    case PCV_ERR_INVALID_ARG: return "invalid argument";
+    case PCV_ERR_NOMEM: return "out of memory";
+    case PCV_ERR_DEVICE: return "device error";
+    case PCV_ERR_STATE: return "invalid state";
+    case PCV_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+const char* pcv_last_error(pcv_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void pcv_destroy(pcv_ctx ctx) {
+  if (!ctx) return;
+  if (!ctx->allocs.empty()) {
+    if (ctx->st) (void)hipStreamSynchronize(ctx->st);
+    else (void)hipDeviceSynchronize();
+  }
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->rb) rocblas_destroy_handle(ctx->rb);
+  delete ctx;
+}
+
+static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, const double* y,
+                            const pcv_folds* fm) {
+  if (!md || !X || !y || !fm) return fail(ctx, PCV_ERR_INVALID_ARG, "null argument");
+  const int64_t n = md->n, p = md->p;
+  if (n <= 0 || p <= 0 || md->K <= 0) return fail(ctx, PCV_ERR_INVALID_ARG, "n, p and K must be positive");
+  if (md->L < 2 || md->L > 64) return fail(ctx, PCV_ERR_INVALID_ARG, "L must be in [2, 64]");
+  if (md->family < 0 || md->family > 3) return fail(ctx, PCV_ERR_INVALID_ARG, "unknown family");
+  if (md->precision < 0 || md->precision > 4) return fail(ctx, PCV_ERR_INVALID_ARG, "unknown precision");
+  if (!(md->step_size > 0) || !std::isfinite(md->step_size)) return fail(ctx, PCV_ERR_INVALID_ARG, "step_size must be > 0");
+  if (md->n_leapfrog < 1) return fail(ctx, PCV_ERR_INVALID_ARG, "n_leapfrog must be >= 1");
+  if (md->batch_size < 1 || md->batches_per_block < 1 || md->n_blocks < 1 || md->n_blocks > MAX_BLOCKS)
+    return fail(ctx, PCV_ERR_INVALID_ARG, "batch_size, batches_per_block >= 1 and 1 <= n_blocks <= 64 required");
+  if (md->n_warmup < 0 || md->chain_offset < 0) return fail(ctx, PCV_ERR_INVALID_ARG, "negative n_warmup or chain_offset");
+  const bool hier = md->family == PCV_FAMILY_HIER_LOGISTIC;
+  if (hier && (md->n_groups <= 0 || !md->group_of)) return fail(ctx, PCV_ERR_INVALID_ARG, "hierarchical family needs groups");
+  const int64_t d = hier ? p + 2 + md->n_groups : p;
+  const int64_t C = static_cast<int64_t>(md->K) * md->L;
+  if (md->chain_offset + C > 0xFFFFFFFFLL) return fail(ctx, PCV_ERR_INVALID_ARG, "global chain ids must fit 32 bits");
+  if (!md->inv_mass || !md->init_pos) return fail(ctx, PCV_ERR_INVALID_ARG, "inv_mass and init_pos are required");
+  if (md->family == PCV_FAMILY_GAUSSIAN && !(md->sigma > 0 && std::isfinite(md->sigma)))
+    return fail(ctx, PCV_ERR_INVALID_ARG, "sigma must be > 0");
+  if (!finite_all(X, n * p) || !finite_all(y, n)) return fail(ctx, PCV_ERR_INVALID_ARG, "X and y must be finite");
+  if (!finite_all(md->init_pos, C * d)) return fail(ctx, PCV_ERR_INVALID_ARG, "init_pos must be finite");
+  for (int64_t j = 0; j < d; ++j)
+    if (!(md->inv_mass[j] > 0) || !std::isfinite(md->inv_mass[j]))
+      return fail(ctx, PCV_ERR_INVALID_ARG, "inv_mass must be > 0");
+  if (md->prior_scale && !hier)
+    for (int64_t j = 0; j < d; ++j)
+      if (!(md->prior_scale[j] > 0) || !std::isfinite(md->prior_scale[j]))
+        return fail(ctx, PCV_ERR_INVALID_ARG, "prior_scale must be > 0");
+  for (int64_t i = 0; i < n; ++i) {
+    const double v = y[i];
+    if ((md->family == PCV_FAMILY_LOGISTIC || hier) && !(v == 0.0 || v == 1.0))
+      return fail(ctx, PCV_ERR_INVALID_ARG, "Bernoulli responses must be 0 or 1");
+    if (md->family == PCV_FAMILY_POISSON && !(v >= 0.0 && v == std::floor(v)))
+      return fail(ctx, PCV_ERR_INVALID_ARG, "Poisson responses must be non-negative integers");
+  }
+  if (hier) {
+    for (int64_t i = 0; i < n; ++i) {
+      const int g = md->group_of[i];
+      if (g < 0 || g >= md->n_groups || (i > 0 && g < md->group_of[i - 1]))
+        return fail(ctx, PCV_ERR_INVALID_ARG, "group_of must be sorted and in [0, n_groups)");
+    }
+  }
+
+  // ---- folds: validate, count, build the test-row lists ------------------
+  const int K = md->K;
+  std::vector<int32_t> test_ptr(K + 1, 0), test_rows;
+  std::vector<int64_t> train_cnt(K, 0);
+  std::vector<int32_t> ivals;
+  if (fm->kind == PCV_FOLDS_INDEX) {
+    if (!fm->fold_index) return fail(ctx, PCV_ERR_INVALID_ARG, "fold_index missing");
+    for (int64_t i = 0; i < n; ++i) {
+      const int f = fm->fold_index[i];
+      if (f < -1 || f >= K) return fail(ctx, PCV_ERR_INVALID_ARG, "fold_index out of range");
+      if (f >= 0) test_ptr[f + 1]++;
+    }
+    for (int k = 0; k < K; ++k) train_cnt[k] = n - test_ptr[k + 1];
+    for (int k = 0; k < K; ++k) test_ptr[k + 1] += test_ptr[k];
+    test_rows.resize(test_ptr[K]);
+    std::vector<int32_t> fill(test_ptr.begin(), test_ptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+      if (fm->fold_index[i] >= 0) test_rows[fill[fm->fold_index[i]]++] = static_cast<int32_t>(i);
+  } else if (fm->kind == PCV_FOLDS_INTERVALS) {
+    if (!fm->intervals) return fail(ctx, PCV_ERR_INVALID_ARG, "intervals missing");
+    if (n > 0x7FFFFFFF) return fail(ctx, PCV_ERR_INVALID_ARG, "n too large for intervals");
+    ivals.resize(4 * K);
+    for (int k = 0; k < K; ++k) {
+      const int64_t* v = fm->intervals + 4 * k;
+      if (v[0] < 0 || v[1] < v[0] || v[1] > n || v[2] < 0 || v[3] < v[2] || v[3] > n)
+        return fail(ctx, PCV_ERR_INVALID_ARG, "intervals out of range");
+      for (int q = 0; q < 4; ++q) ivals[4 * k + q] = static_cast<int32_t>(v[q]);
+      for (int64_t i = v[0]; i < v[1]; ++i) test_rows.push_back(static_cast<int32_t>(i));
+      test_ptr[k + 1] = static_cast<int32_t>(test_rows.size());
+      const int64_t lo = std::min(v[0], v[2]), hi = std::max(v[1], v[3]);
+      const bool overlap = !(v[1] < v[2] || v[3] < v[0]);
+      const int64_t removed = overlap ? hi - lo : (v[1] - v[0]) + (v[3] - v[2]);
+      train_cnt[k] = n - removed;
+    }
+  } else if (fm->kind == PCV_FOLDS_DENSE) {
+    if (!fm->roles) return fail(ctx, PCV_ERR_INVALID_ARG, "roles missing");
+    for (int k = 0; k < K; ++k) {
+      for (int64_t i = 0; i < n; ++i) {
+        const int r = fm->roles[static_cast<int64_t>(k) * n + i];
+        if (r < 0 || r > 2) return fail(ctx, PCV_ERR_INVALID_ARG, "roles must be 0, 1 or 2");
+        if (r == 2) test_rows.push_back(static_cast<int32_t>(i));
+        if (r == 1) train_cnt[k]++;
+      }
+      test_ptr[k + 1] = static_cast<int32_t>(test_rows.size());
+    }
+  } else {
+    return fail(ctx, PCV_ERR_INVALID_ARG, "unknown fold encoding");
+  }
+  for (int k = 0; k < K; ++k) {
+    if (test_ptr[k + 1] == test_ptr[k]) return fail(ctx, PCV_ERR_INVALID_ARG, "a fold has no test row");
+    if (train_cnt[k] <= 0) return fail(ctx, PCV_ERR_INVALID_ARG, "a fold has no training row");
+  }
+
+  // ---- path selection ------------------------------------------------------
+  ctx->prec = md->precision;
+  if (md->precision == PCV_PREC_FP64 || md->precision == PCV_PREC_FP32) {
+    ctx->path = PATH_VALU;
+    ctx->fp64 = md->precision == PCV_PREC_FP64;
+    ctx->pb = valu_pb(p, ctx->fp64);
+    if (!ctx->pb) return fail(ctx, PCV_ERR_UNSUPPORTED, "fused VALU path supports p <= 32 (fp64) or p <= 64 (fp32)");
+  } else if (md->precision == PCV_PREC_BF16X3 || md->precision == PCV_PREC_BF16X5) {
+    ctx->path = PATH_MFMA;
+    ctx->fwd = md->precision == PCV_PREC_BF16X5 ? 5 : 3;
+    if (hier) return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path supports the GLM families");
+    if (p != 64 && p != 128) return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path supports p = 64 or 128");
+  } else {
+    ctx->path = PATH_UNFUSED;
+    if (hier) return fail(ctx, PCV_ERR_UNSUPPORTED, "unfused fp64 path supports the GLM families");
+  }
+
+  // ---- model constants ---------------------------------------------------
+  DevModel& m = ctx->m;
+  m.family = md->family;
+  m.fold_kind = fm->kind;
+  m.n = n;
+  m.p = p;
+  m.d = d;
+  m.C = C;
+  m.K = K;
+  m.L = md->L;
+  m.n_groups = hier ? md->n_groups : 0;
+  m.sigma = md->family == PCV_FAMILY_GAUSSIAN ? md->sigma : 1.0;
+  m.inv_sigma2 = 1.0 / (m.sigma * m.sigma);
+  m.eps = md->step_size;
+  m.S = md->n_leapfrog;
+  m.n_warmup = md->n_warmup;
+  m.b = md->batch_size;
+  m.Gb = md->batches_per_block;
+  m.D = md->n_blocks;
+  m.key0 = static_cast<uint32_t>(md->seed & 0xFFFFFFFFu);
+  m.key1 = static_cast<uint32_t>(md->seed >> 32);
+  m.chain_offset = md->chain_offset;
+
+  std::vector<double> prior_prec(d, 1.0);
+  double prior_const = 0.0;
+  const double half_log_2pi = 0.5 * std::log(2.0 * M_PI);
+  if (hier) {
+    prior_const = -static_cast<double>(d - 1) * half_log_2pi + (std::log(2.0) - half_log_2pi);
+  } else {
+    for (int64_t j = 0; j < d; ++j) {
+      const double s = md->prior_scale ? md->prior_scale[j] : 1.0;
+      prior_prec[j] = 1.0 / (s * s);
+      prior_const += -half_log_2pi - std::log(s);
+    }
+  }
+  ctx->prior_const = prior_const;
+
+  // ---- device data -------------------------------------------------------
+  double *X64, *y64, *minv, *pprec, *rowc, *fconst;
+  TRY(upload(ctx, &X64, X, n * p));
+  TRY(upload(ctx, &y64, y, n));
+  TRY(upload(ctx, &minv, md->inv_mass, d));
+  TRY(upload(ctx, &pprec, prior_prec.data(), d));
+  TRY(dalloc(ctx, &rowc, n));
+  TRY(dalloc(ctx, &fconst, K));
+  std::vector<float> y32(y, y + n);
+  float* y32d;
+  TRY(upload(ctx, &y32d, y32.data(), n));
+  m.X64 = X64;
+  m.y64 = y64;
+  m.y32 = y32d;
+  m.minv = minv;
+  m.prior_prec = pprec;
+  m.rowc = rowc;
+  m.fold_const = fconst;
+  int32_t *tp, *tr;
+  TRY(upload(ctx, &tp, test_ptr.data(), test_ptr.size()));
+  TRY(upload(ctx, &tr, test_rows.data(), test_rows.size()));
+  m.test_ptr = tp;
+  m.test_rows = tr;
+  if (fm->kind == PCV_FOLDS_INDEX) {
+    int32_t* fi;
+    TRY(upload(ctx, &fi, fm->fold_index, n));
+    m.fold_index = fi;
+  } else if (fm->kind == PCV_FOLDS_INTERVALS) {
+    int32_t* iv;
+    TRY(upload(ctx, &iv, ivals.data(), ivals.size()));
+    m.ivals = iv;
+  } else {
+    int8_t* rl;
+    TRY(upload(ctx, &rl, fm->roles, static_cast<size_t>(K) * n));
+    m.roles = rl;
+  }
+  if (hier) {
+    int32_t* go;
+    TRY(upload(ctx, &go, md->group_of, n));
+    m.group_of = go;
+  }
+
+  // chain state and accumulators
+  const size_t dc = static_cast<size_t>(d) * C;
+  TRY(dalloc(ctx, &m.q0, dc));
+  TRY(dalloc(ctx, &m.g0, dc));
+  TRY(dalloc(ctx, &m.q1, dc));
+  TRY(dalloc(ctx, &m.g1, dc));
+  TRY(dalloc(ctx, &m.pm, dc));
+  TRY(dalloc(ctx, &m.logp0, C));
+  TRY(dalloc(ctx, &m.logp1, C));
+  TRY(dalloc(ctx, &m.s0, C));
+  TRY(dalloc(ctx, &m.h0, C));
+  TRY(dalloc(ctx, &m.Z, C));
+  TRY(dalloc(ctx, &m.U, C));
+  TRY(dalloc(ctx, &m.U2, C));
+  TRY(dalloc(ctx, &m.V, C));
+  TRY(dalloc(ctx, &m.V2, C));
+  TRY(dalloc(ctx, &m.bmean, static_cast<size_t>(m.D) * C));
+  TRY(dalloc(ctx, &m.bm2, static_cast<size_t>(m.D) * C));
+  TRY(dalloc(ctx, &m.nacc, C));
+  TRY(dalloc(ctx, &m.ndiv, C));
+  TRY(dalloc(ctx, &ctx->fold_buf, 6 * static_cast<size_t>(K)));
+  TRY(dalloc(ctx, &ctx->dscal, 8));
+  TRY(dalloc(ctx, &ctx->Vpart, C));
+
+  // ---- path-specific buffers -----------------------------------------------
+  if (ctx->path == PATH_VALU) {
+    const int pb = ctx->pb;
+    const int64_t npad = n;
+    if (ctx->fp64) {
+      std::vector<double> xv(static_cast<size_t>(npad) * pb, 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < p; ++j) xv[i * pb + j] = X[i * p + j];
+      double* xd;
+      TRY(upload(ctx, &xd, xv.data(), xv.size()));
+      ctx->Xv = xd;
+    } else {
+      std::vector<float> xv(static_cast<size_t>(npad) * pb, 0.f);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < p; ++j) xv[i * pb + j] = static_cast<float>(X[i * p + j]);
+      float* xd;
+      TRY(upload(ctx, &xd, xv.data(), xv.size()));
+      ctx->Xv = xd;
+      m.X32 = xd;
+    }
+    // waves per workgroup: enough rows per wave, LDS within 64 KB, and the
+    // register budget of wide rows.
+    int W = static_cast<int>(std::min<int64_t>(8, std::max<int64_t>(1, n / 64)));
+    if (pb >= 32) W = std::min(W, 4);
+    while (W > 1 && valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536) --W;
+    if (valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536)
+      return fail(ctx, PCV_ERR_UNSUPPORTED, "too many groups for the fused path");
+    ctx->W = W;
+    std::vector<int32_t> wr(W + 1);
+    for (int w = 0; w <= W; ++w) wr[w] = static_cast<int32_t>(n * w / W);
+    if (hier) {  // align row ranges to group starts so each group has one owner wave
+      for (int w = 1; w < W; ++w) {
+        int64_t i = std::max<int64_t>(wr[w], wr[w - 1]);
+        while (i > wr[w - 1] && i < n && md->group_of[i] == md->group_of[i - 1]) --i;
+        if (i <= wr[w - 1]) {
+          i = std::max<int64_t>(wr[w], wr[w - 1]);
+          while (i < n && i > 0 && md->group_of[i] == md->group_of[i - 1]) ++i;
+        }
+        wr[w] = static_cast<int32_t>(std::min<int64_t>(i, n));
+      }
+      for (int w = 1; w <= W; ++w) wr[w] = std::max(wr[w], wr[w - 1]);
+      wr[W] = static_cast<int32_t>(n);
+    }
+    TRY(upload(ctx, &ctx->wave_rows, wr.data(), wr.size()));
+    m.wave_rows = ctx->wave_rows;
+  } else if (ctx->path == PATH_MFMA) {
+    const int R = mfma_rows_per_tile();
+    ctx->n_tiles = static_cast<int>((n + R - 1) / R);
+    const int n_ct = static_cast<int>((C + mfma_chain_tile() - 1) / mfma_chain_tile());
+    // splits: enough workgroups to fill the chip several times over, each with
+    // a useful number of row tiles
+    int ns = 1;
+    while (static_cast<int64_t>(n_ct) * ns < 4 * 256 && ctx->n_tiles / (ns + 1) >= 8) ++ns;
+    ctx->tiles_per_split = (ctx->n_tiles + ns - 1) / ns;
+    ctx->n_splits = (ctx->n_tiles + ctx->tiles_per_split - 1) / ctx->tiles_per_split;
+    const size_t nfr = static_cast<size_t>(ctx->n_tiles) * mfma_nfrag(static_cast<int>(p)) * 64;
+    TRY(dalloc(ctx, &ctx->Xpk, nfr));
+    CK(launch_mfma_pack(X64, n, static_cast<int>(p), ctx->n_tiles, ctx->Xpk, ctx->st));
+    std::vector<float> ty(static_cast<size_t>(ctx->n_tiles) * R, 0.f);
+    std::vector<int32_t> tf(static_cast<size_t>(ctx->n_tiles) * R, -2);
+    for (int64_t i = 0; i < n; ++i) {
+      ty[i] = static_cast<float>(y[i]);
+      tf[i] = fm->kind == PCV_FOLDS_INDEX ? fm->fold_index[i] : -2;
+    }
+    TRY(upload(ctx, &ctx->ty, ty.data(), ty.size()));
+    TRY(upload(ctx, &ctx->tfid, tf.data(), tf.size()));
+    TRY(dalloc(ctx, &ctx->Gpart, static_cast<size_t>(ctx->n_splits) * p * C));
+    double* vp;
+    TRY(dalloc(ctx, &vp, static_cast<size_t>(ctx->n_splits) * C));
+    ctx->Vpart = vp;
+  } else {
+    if (rocblas_create_handle(&ctx->rb) != rocblas_status_success)
+      return fail(ctx, PCV_ERR_DEVICE, "rocblas_create_handle failed");
+    rocblas_set_stream(ctx->rb, ctx->st);
+    ctx->chunk = std::max<int64_t>(1, std::min<int64_t>(C, (int64_t{1} << 28) / n));
+    TRY(dalloc(ctx, &ctx->eta, static_cast<size_t>(n) * ctx->chunk));
+    TRY(dalloc(ctx, &ctx->Gpart64, dc));
+  }
+
+  // ---- constants, initial state ------------------------------------------
+  CK(launch_rowconst(m, rowc, ctx->st));
+  CK(launch_foldconst(m, prior_const, fconst, ctx->st));
+  double* init_cd;
+  TRY(upload(ctx, &init_cd, md->init_pos, dc));
+  CK(launch_to_dc(init_cd, m.q1, C, d, ctx->st));
+  TRY(eval_q1(ctx));
+  TRY(adopt_q1(ctx));
+  CK(launch_fill(m.Z, -INFINITY, C, ctx->st));
+  CK(launch_fill(m.U, -INFINITY, C, ctx->st));
+  CK(launch_fill(m.U2, -INFINITY, C, ctx->st));
+  CK(launch_fill(m.V, -INFINITY, C, ctx->st));
+  CK(launch_fill(m.V2, -INFINITY, C, ctx->st));
+  CK(launch_fill(m.bmean, 0.0, static_cast<int64_t>(m.D) * C, ctx->st));
+  CK(launch_fill(m.bm2, 0.0, static_cast<int64_t>(m.D) * C, ctx->st));
+  CK(hipMemsetAsync(m.nacc, 0, sizeof(int64_t) * C, ctx->st));
+  CK(hipMemsetAsync(m.ndiv, 0, sizeof(int64_t) * C, ctx->st));
+  CK(hipStreamSynchronize(ctx->st));
+  return PCV_OK;
+}
+
+pcv_status pcv_init(pcv_ctx* out, const pcv_model* model, const double* X, const double* y,
+                    const pcv_folds* fold_masks) {
+  if (!out) return PCV_ERR_INVALID_ARG;
+  *out = nullptr;
+  pcv_ctx ctx = new (std::nothrow) pcv_ctx_s();
+  if (!ctx) return PCV_ERR_NOMEM;
+  pcv_status s = init_impl(ctx, model, X, y, fold_masks);
+  if (s != PCV_OK) {
+    // keep the message available through a static copy: the context dies here
+    static thread_local std::string last;
+    last = ctx->err;
+    std::fprintf(stderr, "pcv_init: %s: %s\n", pcv_status_str(s), last.c_str());
+    pcv_destroy(ctx);
+    return s;
+  }
+  *out = ctx;
+  return PCV_OK;
+}
+
+pcv_status pcv_set_stream(pcv_ctx ctx, void* hip_stream) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  ctx->st = static_cast<hipStream_t>(hip_stream);
+  if (ctx->rb) rocblas_set_stream(ctx->rb, ctx->st);
+  return PCV_OK;
+}
+
+pcv_status pcv_step(pcv_ctx ctx, int64_t n_iter) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (n_iter < 0) return fail(ctx, PCV_ERR_INVALID_ARG, "n_iter must be >= 0");
+  if (ctx->t + n_iter > 0xFFFFFFFFLL) return fail(ctx, PCV_ERR_INVALID_ARG, "iteration counter exceeds 32 bits");
+  if (ctx->path == PATH_VALU) {
+    // one launch runs many whole transitions; chunk to keep launches bounded
+    const int64_t chunk = 256;
+    for (int64_t done = 0; done < n_iter; done += chunk) {
+      const int it = static_cast<int>(std::min<int64_t>(chunk, n_iter - done));
+      if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
+      timing_begin(ctx);
+      CK(launch_valu(ctx->m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, 0, ctx->t + done, it, 0, ctx->st));
+      timing_end(ctx);
+    }
+    ctx->t += n_iter;
+    return PCV_OK;
+  }
+  for (int64_t i = 0; i < n_iter; ++i) {
+    TRY(transition_split(ctx, ctx->t));
+    ctx->t += 1;
+  }
+  return PCV_OK;
+}
+
+static pcv_status run_diag(pcv_ctx ctx, int64_t N, std::vector<double>& fold, double scal[5]) {
+  CK(launch_diag(ctx->m, N, ctx->fold_buf, ctx->dscal, ctx->st));
+  fold.resize(6 * static_cast<size_t>(ctx->m.K));
+  CK(hipMemcpyAsync(fold.data(), ctx->fold_buf, sizeof(double) * fold.size(), hipMemcpyDeviceToHost, ctx->st));
+  CK(hipMemcpyAsync(scal, ctx->dscal, sizeof(double) * 5, hipMemcpyDeviceToHost, ctx->st));
+  CK(hipStreamSynchronize(ctx->st));
+  return PCV_OK;
+}
+
+pcv_status pcv_diagnostics(pcv_ctx ctx, pcv_diag* out) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!out) return fail(ctx, PCV_ERR_INVALID_ARG, "null output");
+  const int64_t N = std::max<int64_t>(0, ctx->t - ctx->m.n_warmup);
+  out->n_iter = ctx->t;
+  out->n_draws = N;
+  if (N < 2) return fail(ctx, PCV_ERR_STATE, "fewer than 2 post-warm-up draws");
+  std::vector<double> fold;
+  double scal[5];
+  TRY(run_diag(ctx, N, fold, scal));
+  const int K = ctx->m.K;
+  const double LN = static_cast<double>(ctx->m.L) * N;
+  out->elpd = scal[0];
+  out->rhat_max = scal[1];
+  out->mcse = std::sqrt(scal[2]);
+  out->ess = LN * scal[3] / scal[4];
+  std::vector<int64_t> na(ctx->m.C), nd(ctx->m.C);
+  CK(hipMemcpy(na.data(), ctx->m.nacc, sizeof(int64_t) * na.size(), hipMemcpyDeviceToHost));
+  CK(hipMemcpy(nd.data(), ctx->m.ndiv, sizeof(int64_t) * nd.size(), hipMemcpyDeviceToHost));
+  int64_t sa = 0, sd = 0;
+  for (int64_t c = 0; c < ctx->m.C; ++c) {
+    sa += na[c];
+    sd += nd[c];
+  }
+  out->accept_rate = static_cast<double>(sa) / (static_cast<double>(ctx->m.C) * N);
+  out->n_divergent = sd;
+  if (out->rhat_fold) std::memcpy(out->rhat_fold, fold.data() + K, sizeof(double) * K);
+  if (out->ess_fold) std::memcpy(out->ess_fold, fold.data() + 4 * static_cast<size_t>(K), sizeof(double) * K);
+  return PCV_OK;
+}
+
+pcv_status pcv_elpd(pcv_ctx ctx, double* elpd, double* mcse, double* elpd_fold, double* mcse_fold) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  const int64_t N = std::max<int64_t>(0, ctx->t - ctx->m.n_warmup);
+  if (N < 1) return fail(ctx, PCV_ERR_STATE, "no post-warm-up draw");
+  std::vector<double> fold;
+  double scal[5];
+  TRY(run_diag(ctx, N, fold, scal));
+  const int K = ctx->m.K;
+  if (elpd) *elpd = scal[0];
+  if (mcse) *mcse = std::sqrt(scal[2]);
+  if (elpd_fold) std::memcpy(elpd_fold, fold.data(), sizeof(double) * K);
+  if (mcse_fold)
+    for (int k = 0; k < K; ++k) mcse_fold[k] = std::sqrt(fold[5 * static_cast<size_t>(K) + k]);
+  return PCV_OK;
+}
+
+pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* rhat_max_rep, double* rhat_rep) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (R < 1 || !rhat_max_rep) return fail(ctx, PCV_ERR_INVALID_ARG, "R >= 1 and an output buffer are required");
+  const int64_t N = std::max<int64_t>(0, ctx->t - ctx->m.n_warmup);
+  if (N < 2) return fail(ctx, PCV_ERR_STATE, "fewer than 2 post-warm-up draws");
+  double *rep, *mx;
+  const size_t nrep = static_cast<size_t>(ctx->m.K) * R;
+  if (hipMalloc(&rep, sizeof(double) * nrep) != hipSuccess) return fail(ctx, PCV_ERR_NOMEM, "hipMalloc failed");
+  if (hipMalloc(&mx, sizeof(double) * R) != hipSuccess) {
+    (void)hipFree(rep);
+    return fail(ctx, PCV_ERR_NOMEM, "hipMalloc failed");
+  }
+  hipError_t e = launch_shuffle(ctx->m, N, R, static_cast<uint32_t>(seed & 0xFFFFFFFFu),
+                                static_cast<uint32_t>(seed >> 32), rep, mx, ctx->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(rhat_max_rep, mx, sizeof(double) * R, hipMemcpyDeviceToHost, ctx->st);
+  if (e == hipSuccess && rhat_rep)
+    e = hipMemcpyAsync(rhat_rep, rep, sizeof(double) * nrep, hipMemcpyDeviceToHost, ctx->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+  (void)hipFree(rep);
+  (void)hipFree(mx);
+  if (e != hipSuccess) {
+    ctx->dead = true;
+    return fail(ctx, PCV_ERR_DEVICE, hipGetErrorString(e));
+  }
+  return PCV_OK;
+}
+
+pcv_status pcv_logdensity_grad(pcv_ctx ctx, const double* theta_dev, double* logp_dev, double* grad_dev,
+                               int32_t want_grad) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!theta_dev || !logp_dev || (want_grad && !grad_dev)) return fail(ctx, PCV_ERR_INVALID_ARG, "null pointer");
+  DevModel& m = ctx->m;
+  CK(launch_to_dc(theta_dev, m.q1, m.C, m.d, ctx->st));
+  TRY(eval_q1(ctx));
+  CK(hipMemcpyAsync(logp_dev, m.logp1, sizeof(double) * m.C, hipMemcpyDeviceToDevice, ctx->st));
+  if (want_grad) CK(launch_to_cd(m.g1, grad_dev, m.C, m.d, ctx->st));
+  CK(hipStreamSynchronize(ctx->st));
+  return PCV_OK;
+}
+
+pcv_status pcv_leapfrog(pcv_ctx ctx, const double* q_dev, const double* p_dev, int32_t n_steps, double* q_out_dev,
+                        double* p_out_dev, double* logp_out_dev, double* grad_out_dev) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!q_dev || !p_dev || !q_out_dev || !p_out_dev || !logp_out_dev || !grad_out_dev || n_steps < 1)
+    return fail(ctx, PCV_ERR_INVALID_ARG, "null pointer or n_steps < 1");
+  DevModel& m = ctx->m;
+  CK(launch_to_dc(q_dev, m.q1, m.C, m.d, ctx->st));
+  CK(launch_to_dc(p_dev, m.pm, m.C, m.d, ctx->st));
+  if (ctx->path == PATH_VALU) {
+    CK(launch_valu(m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, 2, 0, 0, n_steps, ctx->st));
+  } else {
+    TRY(split_partials(ctx, false));
+    TRY(split_reduce(ctx, 0));
+    CK(launch_kick_drift(m, ctx->st));
+    for (int s = 0; s < n_steps; ++s) {
+      const bool last = s == n_steps - 1;
+      TRY(split_partials(ctx, last));
+      TRY(split_reduce(ctx, last ? 2 : 1));
+    }
+    CK(launch_value_finish(m, ctx->Vpart, split_count(ctx), ctx->st));
+  }
+  CK(launch_to_cd(m.q1, q_out_dev, m.C, m.d, ctx->st));
+  CK(launch_to_cd(m.pm, p_out_dev, m.C, m.d, ctx->st));
+  CK(launch_to_cd(m.g1, grad_out_dev, m.C, m.d, ctx->st));
+  CK(hipMemcpyAsync(logp_out_dev, m.logp1, sizeof(double) * m.C, hipMemcpyDeviceToDevice, ctx->st));
+  CK(hipStreamSynchronize(ctx->st));
+  return PCV_OK;
+}
+
+pcv_status pcv_get_state(pcv_ctx ctx, double* theta, double* logp, double* s) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  DevModel& m = ctx->m;
+  CK(hipStreamSynchronize(ctx->st));
+  if (theta) {
+    std::vector<double> dc(static_cast<size_t>(m.d) * m.C);
+    CK(hipMemcpy(dc.data(), m.q0, sizeof(double) * dc.size(), hipMemcpyDeviceToHost));
+    for (int64_t c = 0; c < m.C; ++c)
+      for (int64_t j = 0; j < m.d; ++j) theta[c * m.d + j] = dc[j * m.C + c];
+  }
+  if (logp) CK(hipMemcpy(logp, m.logp0, sizeof(double) * m.C, hipMemcpyDeviceToHost));
+  if (s) CK(hipMemcpy(s, m.s0, sizeof(double) * m.C, hipMemcpyDeviceToHost));
+  return PCV_OK;
+}
+
+pcv_status pcv_set_state(pcv_ctx ctx, const double* theta) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  DevModel& m = ctx->m;
+  if (!theta || !finite_all(theta, m.C * m.d)) return fail(ctx, PCV_ERR_INVALID_ARG, "theta must be finite");
+  std::vector<double> dc(static_cast<size_t>(m.d) * m.C);
+  for (int64_t c = 0; c < m.C; ++c)
+    for (int64_t j = 0; j < m.d; ++j) dc[j * m.C + c] = theta[c * m.d + j];
+  CK(hipStreamSynchronize(ctx->st));
+  CK(hipMemcpy(m.q1, dc.data(), sizeof(double) * dc.size(), hipMemcpyHostToDevice));
+  TRY(eval_q1(ctx));
+  TRY(adopt_q1(ctx));
+  CK(hipStreamSynchronize(ctx->st));
+  return PCV_OK;
+}
+
+pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, double* V, double* V2,
+                                double* blk_mean, double* blk_m2, int64_t* n_accept, int64_t* n_divergent) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  DevModel& m = ctx->m;
+  CK(hipStreamSynchronize(ctx->st));
+  const size_t C = m.C, DC = static_cast<size_t>(m.D) * m.C;
+  if (Z) CK(hipMemcpy(Z, m.Z, sizeof(double) * C, hipMemcpyDeviceToHost));
+  if (U) CK(hipMemcpy(U, m.U, sizeof(double) * C, hipMemcpyDeviceToHost));
+  if (U2) CK(hipMemcpy(U2, m.U2, sizeof(double) * C, hipMemcpyDeviceToHost));
+  if (V) CK(hipMemcpy(V, m.V, sizeof(double) * C, hipMemcpyDeviceToHost));
+  if (V2) CK(hipMemcpy(V2, m.V2, sizeof(double) * C, hipMemcpyDeviceToHost));
+  if (blk_mean) CK(hipMemcpy(blk_mean, m.bmean, sizeof(double) * DC, hipMemcpyDeviceToHost));
+  if (blk_m2) CK(hipMemcpy(blk_m2, m.bm2, sizeof(double) * DC, hipMemcpyDeviceToHost));
+  if (n_accept) CK(hipMemcpy(n_accept, m.nacc, sizeof(int64_t) * C, hipMemcpyDeviceToHost));
+  if (n_divergent) CK(hipMemcpy(n_divergent, m.ndiv, sizeof(int64_t) * C, hipMemcpyDeviceToHost));
+  return PCV_OK;
+}
+
+pcv_status pcv_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n, uint32_t* out) {
+  if (n < 0 || (n > 0 && !out)) return PCV_ERR_INVALID_ARG;
+  if (n == 0) return PCV_OK;
+  uint32_t* d = nullptr;
+  if (hipMalloc(&d, sizeof(uint32_t) * 4 * n) != hipSuccess) return PCV_ERR_NOMEM;
+  hipError_t e = launch_philox(static_cast<uint32_t>(seed & 0xFFFFFFFFu), static_cast<uint32_t>(seed >> 32), c0, c1,
+                               c2, c3, n, d, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(out, d, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return e == hipSuccess ? PCV_OK : PCV_ERR_DEVICE;
+}
+
+pcv_status pcv_timing_enable(pcv_ctx ctx, int32_t on) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  ctx->timing = on != 0;
+  return PCV_OK;
+}
+
+pcv_status pcv_timing_read(pcv_ctx ctx, double* ms_sum, int64_t* n_launches, const char** kernel_name,
+                           int32_t reset) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  CK(hipStreamSynchronize(ctx->st));
+  timing_collect(ctx);
+  if (ms_sum) *ms_sum = ctx->ms_acc;
+  if (n_launches) *n_launches = ctx->n_launch;
+  if (kernel_name) *kernel_name = kGradKernelName[ctx->path];
+  if (reset) {
+    ctx->ms_acc = 0.0;
+    ctx->n_launch = 0;
+  }
+  return PCV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,411 @@
+// Per-chain kernels of the split (multi-launch) paths, diagnostics, and
+// initialisation helpers.
+#include "pcv_internal.h"
+
+namespace pcv {
+
+constexpr int TPB = 256;
+
+static inline int nblocks(int64_t n, int tpb = TPB) { return static_cast<int>((n + tpb - 1) / tpb); }
+
+// ---- transition pieces -----------------------------------------------------
+
+__global__ void k_momentum(DevModel m, int64_t t) {
+  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (c < m.C) momentum_and_first_drift(m, c, t);
+}
+
+// Sum partial gradients over row splits (fixed order), add the prior, and
+// apply the leapfrog update.  mode 0: store the gradient only; 1: kick and
+// drift; 2: final half kick.
+template <typename PT>
+__global__ void k_reduce(DevModel m, const PT* __restrict__ Gpart, int n_splits, int mode) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= m.d * m.C) return;
+  const int64_t j = idx / m.C, c = idx - j * m.C;
+  double G = 0.0;
+  for (int s = 0; s < n_splits; ++s) G += static_cast<double>(Gpart[(static_cast<int64_t>(s) * m.d + j) * m.C + c]);
+  const double g = G + prior_grad(m, m.q1[idx], j);
+  if (mode == 0) m.g1[idx] = g;
+  else leapfrog_update(m, c, j, g, mode == 2);
+}
+
+__device__ __forceinline__ double value_finish(const DevModel& m, const double* Vpart, int n_splits, int64_t c) {
+  double v = 0.0;
+  for (int s = 0; s < n_splits; ++s) v += Vpart[static_cast<int64_t>(s) * m.C + c];
+  return v + m.fold_const[c / m.L] + prior_quad(m, m.q1, c);
+}
+
+__global__ void k_value_finish(DevModel m, const double* Vpart, int n_splits) {
+  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (c < m.C) m.logp1[c] = value_finish(m, Vpart, n_splits, c);
+}
+
+template <int FAM>
+__global__ void k_accept(DevModel m, const double* Vpart, int n_splits, int64_t t) {
+  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (c >= m.C) return;
+  m.logp1[c] = value_finish(m, Vpart, n_splits, c);
+  accept_and_accumulate<FAM>(m, c, t);
+}
+
+// Log predictive at q0 for every chain (initialisation and set_state).
+template <int FAM>
+__global__ void k_logpred(DevModel m) {
+  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (c < m.C) m.s0[c] = log_pred_fold<FAM>(m, m.q0, c);
+}
+
+// Masked residual of the unfused fp64 path, eta [n][cc] column-major (one
+// column per chain), in place; one block per chain column; value partial.
+template <int FAM>
+__global__ void k_unfused_resid(DevModel m, double* __restrict__ eta, int64_t c0, int64_t cc, double* Vpart,
+                                int want_value) {
+  __shared__ double red[TPB];
+  const int64_t col = blockIdx.x;
+  if (col >= cc) return;
+  const int64_t c = c0 + col;
+  const int k = static_cast<int>(c / m.L);
+  double v = 0.0;
+  double* e = eta + col * m.n;
+  for (int64_t i = threadIdx.x; i < m.n; i += blockDim.x) {
+    const bool train = row_role(m, i, k) == 1;
+    const double et = e[i];
+    const double y = m.y64[i];
+    if (want_value && train) v += ell0_64<FAM>(y, et, m.inv_sigma2);
+    e[i] = train ? resid64<FAM>(y, et, m.inv_sigma2) : 0.0;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && want_value) Vpart[c] = red[0];
+}
+
+// ---- initialisation helpers ------------------------------------------------
+
+__global__ void k_rowconst(DevModel m, double* rowc) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= m.n) return;
+  double v = 0.0;
+  if (m.family == FAM_GAUSS) v = -0.5 * log(2.0 * M_PI / m.inv_sigma2);
+  else if (m.family == FAM_POIS) v = -lgamma(m.y64[i] + 1.0);
+  rowc[i] = v;
+}
+
+// fold_const[k] = sum over train rows of the row constant + prior constant.
+__global__ void k_foldconst(DevModel m, double prior_const, double* fold_const) {
+  __shared__ double red[TPB];
+  const int k = blockIdx.x;
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < m.n; i += blockDim.x)
+    if (row_role(m, i, k) == 1) v += m.rowc[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) fold_const[k] = red[0] + prior_const;
+}
+
+// [C][d] chain-major <-> [d][C]
+__global__ void k_to_dc(const double* __restrict__ src, double* __restrict__ dst, int64_t C, int64_t d) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= C * d) return;
+  const int64_t j = idx / C, c = idx - j * C;
+  dst[idx] = src[c * d + j];
+}
+__global__ void k_to_cd(const double* __restrict__ src, double* __restrict__ dst, int64_t C, int64_t d) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= C * d) return;
+  const int64_t c = idx / d, j = idx - c * d;
+  dst[idx] = src[j * C + c];
+}
+
+__global__ void k_fill(double* p, double v, int64_t n) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                         uint32_t* out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const W4 w = philox4x32_10(W4{c0, c1, c2, c3 + static_cast<uint32_t>(i)}, k0, k1);
+  out[4 * i + 0] = w.x;
+  out[4 * i + 1] = w.y;
+  out[4 * i + 2] = w.z;
+  out[4 * i + 3] = w.w;
+}
+
+// ---- diagnostics (fp64) ----------------------------------------------------
+// Per fold: elpd_k, Rhat_k, sigma2_k/f_k^2 (batch means), s2_k/f_k^2 (pooled),
+// ESS_k, Var(f_k)/f_k^2.  Every exponential is taken relative to the fold's
+// largest log term.
+struct FoldDiag {
+  double* elpd;
+  double* rhat;
+  double* sig2rel;
+  double* s2rel;
+  double* ess;
+  double* varrel;
+};
+
+__device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, double nb, double mb, double m2b) {
+  const double nt = n + nb;
+  if (nt <= 0.0) return;
+  const double delta = mb - mean;
+  mean = mean + delta * (nb / nt);
+  m2 = m2 + m2b + delta * delta * n * nb / nt;
+  n = nt;
+}
+
+__device__ __forceinline__ double block_count(const DevModel& m, int64_t N, int dd) {
+  const int64_t per = static_cast<int64_t>(m.Gb) * m.b;
+  int64_t lo = dd * per, hi = (dd == m.D - 1) ? N : (dd + 1) * per;
+  if (hi > N) hi = N;
+  return hi > lo ? static_cast<double>(hi - lo) : 0.0;
+}
+
+__device__ double rhat_of(double N, const double* mean, const double* m2, int L) {
+  double W = 0.0, grand = 0.0;
+  for (int l = 0; l < L; ++l) {
+    W += m2[l] / (N - 1.0);
+    grand += mean[l];
+  }
+  W /= L;
+  grand /= L;
+  double B = 0.0;
+  for (int l = 0; l < L; ++l) B += (mean[l] - grand) * (mean[l] - grand);
+  B *= N / (L - 1.0);
+  return sqrt((N - 1.0) / N + B / (N * W));
+}
+
+constexpr int MAX_L = 64;
+
+__global__ void k_diag_fold(DevModel m, int64_t N, FoldDiag o) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.K) return;
+  const int L = m.L;
+  const int64_t c0 = static_cast<int64_t>(k) * L;
+  const double LN = static_cast<double>(L) * N;
+  // elpd and pooled variance of f = e^s
+  double ua[MAX_L];
+  double mu = -INFINITY;
+  for (int l = 0; l < L; ++l) {
+    ua[l] = log_add_exp(m.U[c0 + l], m.Z[c0 + l]);
+    mu = fmax(mu, ua[l]);
+  }
+  double s1 = 0.0, s2 = 0.0;
+  for (int l = 0; l < L; ++l) {
+    s1 += exp(ua[l] - mu);
+    s2 += exp(m.U2[c0 + l] - 2.0 * mu);
+  }
+  const double log_fhat = mu + log(s1) - log(LN);
+  o.elpd[k] = log_fhat;
+  const double br = s2 - s1 * s1 / LN;
+  const double s2rel = exp(2.0 * mu + log(fmax(br, 0.0)) - log(LN - 1.0) - 2.0 * log_fhat);
+  o.s2rel[k] = s2rel;
+  // batch means
+  const int64_t a = N / m.b;
+  double sig2rel = NAN;
+  if (a >= 1 && L * a > 1) {
+    double mv = -INFINITY;
+    for (int l = 0; l < L; ++l) mv = fmax(mv, m.V[c0 + l]);
+    double v1 = 0.0, v2 = 0.0;
+    for (int l = 0; l < L; ++l) {
+      v1 += exp(m.V[c0 + l] - mv);
+      v2 += exp(m.V2[c0 + l] - 2.0 * mv);
+    }
+    const double La = static_cast<double>(L) * a;
+    const double bv = v2 - v1 * v1 / La;
+    sig2rel = exp(log(static_cast<double>(m.b)) - log(La - 1.0) + 2.0 * mv + log(fmax(bv, 0.0)) - 2.0 * log_fhat);
+  }
+  o.sig2rel[k] = sig2rel;
+  o.varrel[k] = sig2rel / LN;
+  o.ess[k] = LN * s2rel / sig2rel;
+  // Rhat from Welford blocks
+  double cm[MAX_L], cm2[MAX_L];
+  for (int l = 0; l < L; ++l) {
+    double n = 0.0, mean = 0.0, m2 = 0.0;
+    for (int dd = 0; dd < m.D; ++dd) {
+      const int64_t off = static_cast<int64_t>(dd) * m.C + c0 + l;
+      chan_merge(n, mean, m2, block_count(m, N, dd), m.bmean[off], m.bm2[off]);
+    }
+    cm[l] = mean;
+    cm2[l] = m2;
+  }
+  o.rhat[k] = N >= 2 ? rhat_of(static_cast<double>(N), cm, cm2, L) : NAN;
+}
+
+// Fold-level sums and max, one block, fixed-order tree (deterministic).
+// out: [0] sum elpd, [1] max rhat, [2] sum varrel, [3] sum s2rel, [4] sum sig2rel
+__global__ void k_diag_reduce(int K, FoldDiag o, double* out) {
+  __shared__ double r[5][1024];
+  double a0 = 0.0, a1 = -INFINITY, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    a0 += o.elpd[k];
+    a1 = fmax(a1, o.rhat[k]);
+    a2 += o.varrel[k];
+    a3 += o.s2rel[k];
+    a4 += o.sig2rel[k];
+  }
+  r[0][threadIdx.x] = a0;
+  r[1][threadIdx.x] = a1;
+  r[2][threadIdx.x] = a2;
+  r[3][threadIdx.x] = a3;
+  r[4][threadIdx.x] = a4;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      r[0][threadIdx.x] += r[0][threadIdx.x + s];
+      r[1][threadIdx.x] = fmax(r[1][threadIdx.x], r[1][threadIdx.x + s]);
+      r[2][threadIdx.x] += r[2][threadIdx.x + s];
+      r[3][threadIdx.x] += r[3][threadIdx.x + s];
+      r[4][threadIdx.x] += r[4][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 5; ++q) out[q] = r[q][0];
+}
+
+// Block-shuffle replicate r of fold k (Section 4.2): chain slot l takes block
+// dd from chain floor(u * L) of the same fold, u from Philox(fold, r, TAG, l*D+dd).
+__global__ void k_shuffle(DevModel m, int64_t N, int R, uint32_t s0, uint32_t s1, double* rep) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(m.K) * R) return;
+  const int k = static_cast<int>(idx / R), r = static_cast<int>(idx - static_cast<int64_t>(k) * R);
+  const int L = m.L;
+  const uint32_t fold_global = static_cast<uint32_t>(m.chain_offset / L + k);
+  double cm[MAX_L], cm2[MAX_L];
+  for (int l = 0; l < L; ++l) {
+    double n = 0.0, mean = 0.0, m2 = 0.0;
+    for (int dd = 0; dd < m.D; ++dd) {
+      const W4 w = philox4x32_10(W4{fold_global, static_cast<uint32_t>(r), TAG_SHUFFLE,
+                                    static_cast<uint32_t>(l * m.D + dd)}, s0, s1);
+      int src = static_cast<int>(floor(uniform01(w.x, w.y) * L));
+      if (src > L - 1) src = L - 1;
+      const int64_t off = static_cast<int64_t>(dd) * m.C + static_cast<int64_t>(k) * L + src;
+      chan_merge(n, mean, m2, block_count(m, N, dd), m.bmean[off], m.bm2[off]);
+    }
+    cm[l] = mean;
+    cm2[l] = m2;
+  }
+  rep[idx] = rhat_of(static_cast<double>(N), cm, cm2, L);
+}
+
+__global__ void k_shuffle_max(int K, int R, const double* rep, double* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double v = -INFINITY;
+  for (int k = 0; k < K; ++k) v = fmax(v, rep[static_cast<int64_t>(k) * R + r]);
+  out[r] = v;
+}
+
+// First half kick and drift from (q1, pm) with the gradient g1 at q1 (leapfrog hook).
+__global__ void k_kick_drift(DevModel m) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= m.d * m.C) return;
+  const int64_t j = idx / m.C;
+  const double p = m.pm[idx] + 0.5 * m.eps * m.g1[idx];
+  m.pm[idx] = p;
+  m.q1[idx] += m.eps * m.minv[j] * p;
+}
+
+// ---- host launchers --------------------------------------------------------
+
+#define PCV_FAM_DISPATCH(fam, KERNEL, grid, block, st, ...)                                       \
+  do {                                                                                           \
+    switch (fam) {                                                                               \
+      case FAM_GAUSS: hipLaunchKernelGGL((KERNEL<FAM_GAUSS>), grid, block, 0, st, __VA_ARGS__); break; \
+      case FAM_LOGIT: hipLaunchKernelGGL((KERNEL<FAM_LOGIT>), grid, block, 0, st, __VA_ARGS__); break; \
+      case FAM_POIS: hipLaunchKernelGGL((KERNEL<FAM_POIS>), grid, block, 0, st, __VA_ARGS__); break;   \
+      case FAM_HIER: hipLaunchKernelGGL((KERNEL<FAM_HIER>), grid, block, 0, st, __VA_ARGS__); break;   \
+    }                                                                                            \
+  } while (0)
+
+hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st) {
+  hipLaunchKernelGGL(k_momentum, dim3(nblocks(m.C)), dim3(TPB), 0, st, m, t);
+  return hipGetLastError();
+}
+hipError_t launch_kick_drift(const DevModel& m, hipStream_t st) {
+  hipLaunchKernelGGL(k_kick_drift, dim3(nblocks(m.d * m.C)), dim3(TPB), 0, st, m);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_f32(const DevModel& m, const float* G, int ns, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce<float>, dim3(nblocks(m.d * m.C)), dim3(TPB), 0, st, m, G, ns, mode);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_f64(const DevModel& m, const double* G, int ns, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce<double>, dim3(nblocks(m.d * m.C)), dim3(TPB), 0, st, m, G, ns, mode);
+  return hipGetLastError();
+}
+hipError_t launch_value_finish(const DevModel& m, const double* V, int ns, hipStream_t st) {
+  hipLaunchKernelGGL(k_value_finish, dim3(nblocks(m.C)), dim3(TPB), 0, st, m, V, ns);
+  return hipGetLastError();
+}
+hipError_t launch_accept(const DevModel& m, const double* V, int ns, int64_t t, hipStream_t st) {
+  PCV_FAM_DISPATCH(m.family, k_accept, dim3(nblocks(m.C)), dim3(TPB), st, m, V, ns, t);
+  return hipGetLastError();
+}
+hipError_t launch_logpred(const DevModel& m, hipStream_t st) {
+  PCV_FAM_DISPATCH(m.family, k_logpred, dim3(nblocks(m.C)), dim3(TPB), st, m);
+  return hipGetLastError();
+}
+hipError_t launch_unfused_resid(const DevModel& m, double* eta, int64_t c0, int64_t cc, double* V, int want_value,
+                                hipStream_t st) {
+  PCV_FAM_DISPATCH(m.family, k_unfused_resid, dim3(static_cast<unsigned>(cc)), dim3(TPB), st, m, eta, c0, cc, V,
+                   want_value);
+  return hipGetLastError();
+}
+hipError_t launch_rowconst(const DevModel& m, double* rowc, hipStream_t st) {
+  hipLaunchKernelGGL(k_rowconst, dim3(nblocks(m.n)), dim3(TPB), 0, st, m, rowc);
+  return hipGetLastError();
+}
+hipError_t launch_foldconst(const DevModel& m, double prior_const, double* fc, hipStream_t st) {
+  hipLaunchKernelGGL(k_foldconst, dim3(m.K), dim3(TPB), 0, st, m, prior_const, fc);
+  return hipGetLastError();
+}
+hipError_t launch_to_dc(const double* src, double* dst, int64_t C, int64_t d, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_dc, dim3(nblocks(C * d)), dim3(TPB), 0, st, src, dst, C, d);
+  return hipGetLastError();
+}
+hipError_t launch_to_cd(const double* src, double* dst, int64_t C, int64_t d, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_cd, dim3(nblocks(C * d)), dim3(TPB), 0, st, src, dst, C, d);
+  return hipGetLastError();
+}
+hipError_t launch_fill(double* p, double v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(TPB), 0, st, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int64_t n,
+                         uint32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_philox, dim3(nblocks(n)), dim3(TPB), 0, st, k0, k1, c0, c1, c2, c3, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_diag(const DevModel& m, int64_t N, double* fold_buf, double* out, hipStream_t st) {
+  FoldDiag o;
+  o.elpd = fold_buf;
+  o.rhat = fold_buf + m.K;
+  o.sig2rel = fold_buf + 2 * static_cast<int64_t>(m.K);
+  o.s2rel = fold_buf + 3 * static_cast<int64_t>(m.K);
+  o.ess = fold_buf + 4 * static_cast<int64_t>(m.K);
+  o.varrel = fold_buf + 5 * static_cast<int64_t>(m.K);
+  hipLaunchKernelGGL(k_diag_fold, dim3(nblocks(m.K, 64)), dim3(64), 0, st, m, N, o);
+  hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(1024), 0, st, m.K, o, out);
+  return hipGetLastError();
+}
+hipError_t launch_shuffle(const DevModel& m, int64_t N, int R, uint32_t s0, uint32_t s1, double* rep,
+                          double* repmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_shuffle, dim3(nblocks(static_cast<int64_t>(m.K) * R)), dim3(TPB), 0, st, m, N, R, s0, s1,
+                     rep);
+  hipLaunchKernelGGL(k_shuffle_max, dim3(nblocks(R)), dim3(TPB), 0, st, m.K, R, rep, repmax);
+  return hipGetLastError();
+}
+
+}  // namespace pcv

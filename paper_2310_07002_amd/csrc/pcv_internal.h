@@ -1,0 +1,301 @@
+// Internal declarations of the PCV library: context, device buffers and the
+// device-side building blocks shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pcv.h"
+
+namespace pcv {
+
+constexpr uint32_t TAG_MOMENTUM = 1;
+constexpr uint32_t TAG_ACCEPT = 2;
+constexpr uint32_t TAG_SHUFFLE = 3;
+constexpr double DIVERGENCE_THRESHOLD = 1000.0;
+constexpr int MAX_BLOCKS = 64;
+
+// ----------------------------------------------------------------------------
+// Kernel argument bundle (plain device pointers; passed by value).
+// ----------------------------------------------------------------------------
+struct DevModel {
+  int family, fold_kind;
+  int64_t n, p, d, C;
+  int K, L, n_groups;
+  double sigma, inv_sigma2, eps;
+  int S;
+  int64_t n_warmup;
+  int b, Gb, D;
+  uint32_t key0, key1;
+  int64_t chain_offset;
+  // data
+  const double* X64;      // [n][p]
+  const float* X32;       // [n][p] (fp32 VALU path)
+  const double* y64;      // [n]
+  const float* y32;       // [n]
+  const double* rowc;     // [n] per-row log-likelihood constant
+  const int32_t* fold_index;  // INDEX [n]
+  const int32_t* ivals;       // INTERVALS [K][4]
+  const int8_t* roles;        // DENSE [K][n]
+  const int32_t* test_ptr;    // [K+1]
+  const int32_t* test_rows;   // [nnz]
+  const int32_t* group_of;    // HIER [n]
+  const int32_t* wave_rows;   // VALU row partition [W+1]
+  const double* minv;         // [d]
+  const double* prior_prec;   // [d] 1/scale^2
+  const double* fold_const;   // [K]
+  // chain state, [d][C] (chain index fastest)
+  double *q0, *g0, *q1, *g1, *pm;
+  double *logp0, *logp1, *s0, *h0;
+  // accumulators
+  double *Z, *U, *U2, *V, *V2, *bmean, *bm2;   // [C], [D][C]
+  int64_t *nacc, *ndiv;
+};
+
+// ----------------------------------------------------------------------------
+// Device helpers
+// ----------------------------------------------------------------------------
+struct W4 {
+  uint32_t x, y, z, w;
+};
+
+// Philox4x32 with ten rounds (Salmon et al., SC'11).
+__device__ __forceinline__ W4 philox4x32_10(W4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = W4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+  }
+  return c;
+}
+
+// Two 32-bit words -> double strictly inside (0,1): top 52 bits, centred in their cell.
+__device__ __forceinline__ double uniform01(uint32_t w0, uint32_t w1) {
+  const uint64_t b = (static_cast<uint64_t>(w0) << 32) | w1;
+  return static_cast<double>(b >> 12) * 0x1p-52 + 0x1p-53;
+}
+
+__device__ __forceinline__ double log_add_exp(double a, double b) {
+  if (a == -INFINITY) return b;
+  if (b == -INFINITY) return a;
+  const double m = a > b ? a : b;
+  return m + log1p(exp(-fabs(a - b)));
+}
+
+enum { FAM_GAUSS = 0, FAM_LOGIT = 1, FAM_POIS = 2, FAM_HIER = 3 };
+
+// d l(y, eta) / d eta and l(y, eta) minus its per-row constant.
+template <int FAM>
+__device__ __forceinline__ double resid64(double y, double eta, double inv_sigma2) {
+  if (FAM == FAM_GAUSS) return (y - eta) * inv_sigma2;
+  if (FAM == FAM_POIS) return y - exp(eta);
+  return y - 1.0 / (1.0 + exp(-eta));
+}
+template <int FAM>
+__device__ __forceinline__ double ell0_64(double y, double eta, double inv_sigma2) {
+  if (FAM == FAM_GAUSS) {
+    const double e = y - eta;
+    return -0.5 * e * e * inv_sigma2;
+  }
+  if (FAM == FAM_POIS) return y * eta - exp(eta);
+  return y * eta - (fmax(eta, 0.0) + log1p(exp(-fabs(eta))));
+}
+template <int FAM>
+__device__ __forceinline__ float resid32(float y, float eta, float inv_sigma2) {
+  if (FAM == FAM_GAUSS) return (y - eta) * inv_sigma2;
+  if (FAM == FAM_POIS) return y - __expf(eta);
+  return y - 1.0f / (1.0f + __expf(-eta));
+}
+template <int FAM>
+__device__ __forceinline__ float ell0_32(float y, float eta, float inv_sigma2) {
+  if (FAM == FAM_GAUSS) {
+    const float e = y - eta;
+    return -0.5f * e * e * inv_sigma2;
+  }
+  if (FAM == FAM_POIS) return y * eta - __expf(eta);
+  return y * eta - (fmaxf(eta, 0.0f) + log1pf(__expf(-fabsf(eta))));
+}
+
+// Role of row i in fold k: 0 excluded, 1 train, 2 test.
+__device__ __forceinline__ int row_role(const DevModel& m, int64_t i, int k) {
+  if (m.fold_kind == PCV_FOLDS_INDEX) {
+    const int f = m.fold_index[i];
+    return f == k ? 2 : 1;
+  }
+  if (m.fold_kind == PCV_FOLDS_INTERVALS) {
+    const int32_t* v = m.ivals + 4 * k;
+    if (i >= v[0] && i < v[1]) return 2;
+    if (i >= v[2] && i < v[3]) return 0;
+    return 1;
+  }
+  return m.roles[static_cast<int64_t>(k) * m.n + i];
+}
+
+// ----------------------------------------------------------------------------
+// Per-chain device routines shared by the fused and the split paths.
+// State arrays are [d][C]; c is the local chain index.
+// ----------------------------------------------------------------------------
+
+// eta of row i for chain c at position q ([d][C]) in fp64.
+__device__ __forceinline__ double eta_row64(const DevModel& m, const double* q, int64_t c, int64_t i) {
+  const double* x = m.X64 + i * m.p;
+  double e = 0.0;
+  for (int64_t j = 0; j < m.p; ++j) e += x[j] * q[j * m.C + c];
+  if (m.family == FAM_HIER) {
+    const double mu = q[m.p * m.C + c];
+    const double tau = exp(q[(m.p + 1) * m.C + c]);
+    e += mu + tau * q[(m.p + 2 + m.group_of[i]) * m.C + c];
+  }
+  return e;
+}
+
+// Joint log density of the fold's test rows at q (fp64, with constants).
+template <int FAM>
+__device__ double log_pred_fold(const DevModel& m, const double* q, int64_t c) {
+  const int k = static_cast<int>(c / m.L);
+  double s = 0.0;
+  for (int t = m.test_ptr[k]; t < m.test_ptr[k + 1]; ++t) {
+    const int64_t i = m.test_rows[t];
+    const double eta = eta_row64(m, q, c, i);
+    s += ell0_64<FAM>(m.y64[i], eta, m.inv_sigma2) + m.rowc[i];
+  }
+  return s;
+}
+
+// Prior: returns the non-constant part of log prior at q (constants are in fold_const).
+__device__ __forceinline__ double prior_quad(const DevModel& m, const double* q, int64_t c) {
+  double v = 0.0;
+  if (m.family == FAM_HIER) {
+    for (int64_t j = 0; j < m.d; ++j) {
+      if (j == m.p + 1) continue;
+      const double t = q[j * m.C + c];
+      v -= 0.5 * t * t;
+    }
+    const double u = q[(m.p + 1) * m.C + c];
+    const double tau = exp(u);
+    v += -0.5 * tau * tau + u;
+    return v;
+  }
+  for (int64_t j = 0; j < m.d; ++j) {
+    const double t = q[j * m.C + c];
+    v -= 0.5 * t * t * m.prior_prec[j];
+  }
+  return v;
+}
+
+__device__ __forceinline__ double prior_grad(const DevModel& m, double theta, int64_t j) {
+  if (m.family == FAM_HIER) {
+    if (j == m.p + 1) return -exp(2.0 * theta) + 1.0;
+    return -theta;
+  }
+  return -theta * m.prior_prec[j];
+}
+
+// Momentum refresh, first half kick and first drift of one transition.
+__device__ __forceinline__ void momentum_and_first_drift(const DevModel& m, int64_t c, int64_t t) {
+  const uint32_t gc = static_cast<uint32_t>(m.chain_offset + c);
+  double k0 = 0.0;
+  for (int64_t jb = 0; 2 * jb < m.d; ++jb) {
+    const W4 w = philox4x32_10(W4{gc, static_cast<uint32_t>(t), TAG_MOMENTUM, static_cast<uint32_t>(jb)},
+                               m.key0, m.key1);
+    const double u1 = uniform01(w.x, w.y), u2 = uniform01(w.z, w.w);
+    const double r = sqrt(-2.0 * log(u1));
+    const double ang = 2.0 * M_PI * u2;
+    const double z[2] = {r * cos(ang), r * sin(ang)};
+    for (int h = 0; h < 2; ++h) {
+      const int64_t j = 2 * jb + h;
+      if (j >= m.d) break;
+      const double mi = m.minv[j];
+      double p = z[h] / sqrt(mi);
+      k0 += 0.5 * mi * p * p;
+      const int64_t o = j * m.C + c;
+      p += 0.5 * m.eps * m.g0[o];
+      m.pm[o] = p;
+      m.q1[o] = m.q0[o] + m.eps * mi * p;
+    }
+  }
+  m.h0[c] = -m.logp0[c] + k0;
+}
+
+// Leapfrog update after a gradient evaluation at q1 (g already includes the prior).
+// last: half kick only; otherwise full kick and drift.
+__device__ __forceinline__ void leapfrog_update(const DevModel& m, int64_t c, int64_t j, double g, bool last) {
+  const int64_t o = j * m.C + c;
+  m.g1[o] = g;
+  double p = m.pm[o];
+  if (last) {
+    p += 0.5 * m.eps * g;
+    m.pm[o] = p;
+  } else {
+    p += m.eps * g;
+    m.pm[o] = p;
+    m.q1[o] += m.eps * m.minv[j] * p;
+  }
+}
+
+// Welford / log-sum-exp accumulation of post-warm-up draw i (Algorithm A2).
+__device__ __forceinline__ void accumulate_draw(const DevModel& m, int64_t c, int64_t i, double s) {
+  m.Z[c] = log_add_exp(m.Z[c], s);
+  m.U2[c] = log_add_exp(m.U2[c], 2.0 * s);
+  const int64_t per_block = static_cast<int64_t>(m.Gb) * m.b;
+  int64_t blk = i / per_block;
+  if (blk > m.D - 1) blk = m.D - 1;
+  const double cnt = static_cast<double>(i - blk * per_block + 1);
+  const int64_t o = blk * m.C + c;
+  const double mean = m.bmean[o];
+  const double delta = s - mean;
+  const double nm = mean + delta / cnt;
+  m.bmean[o] = nm;
+  m.bm2[o] += delta * (s - nm);
+  if ((i + 1) % m.b == 0) {
+    const double z = m.Z[c];
+    const double lb = log(static_cast<double>(m.b));
+    m.U[c] = log_add_exp(m.U[c], z);
+    m.V[c] = log_add_exp(m.V[c], z - lb);
+    m.V2[c] = log_add_exp(m.V2[c], 2.0 * z - 2.0 * lb);
+    m.Z[c] = -INFINITY;
+  }
+}
+
+// Metropolis test at the end of a trajectory (q1, pm, logp1, g1), state
+// selection, log predictive at the new state and accumulation.
+template <int FAM>
+__device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
+  double k1 = 0.0;
+  for (int64_t j = 0; j < m.d; ++j) {
+    const double p = m.pm[j * m.C + c];
+    k1 += 0.5 * m.minv[j] * p * p;
+  }
+  const double h1 = -m.logp1[c] + k1;
+  const double log_ratio = m.h0[c] - h1;
+  const uint32_t gc = static_cast<uint32_t>(m.chain_offset + c);
+  const W4 w = philox4x32_10(W4{gc, static_cast<uint32_t>(t), TAG_ACCEPT, 0u}, m.key0, m.key1);
+  const double u = uniform01(w.x, w.y);
+  const bool finite = isfinite(log_ratio);
+  const bool accepted = finite && (log(u) < log_ratio);
+  const bool divergent = !finite || (-log_ratio > DIVERGENCE_THRESHOLD);
+  if (accepted) {
+    for (int64_t j = 0; j < m.d; ++j) {
+      const int64_t o = j * m.C + c;
+      m.q0[o] = m.q1[o];
+      m.g0[o] = m.g1[o];
+    }
+    m.logp0[c] = m.logp1[c];
+    m.s0[c] = log_pred_fold<FAM>(m, m.q0, c);
+  }
+  if (t >= m.n_warmup) {
+    accumulate_draw(m, c, t - m.n_warmup, m.s0[c]);
+    m.nacc[c] += accepted ? 1 : 0;
+    m.ndiv[c] += divergent ? 1 : 0;
+  }
+}
+
+}  // namespace pcv

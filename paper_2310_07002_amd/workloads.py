@@ -45,7 +45,8 @@ HIER_LOGISTIC = 3
 PREC_FP64 = 0
 PREC_FP32 = 1
 PREC_BF16X3 = 2
-PREC_FP64_UNFUSED = 3
+PREC_BF16X5 = 3
+PREC_FP64_UNFUSED = 4
 
 # Fold encodings.
 FOLDS_INDEX = 0

@@ -1,0 +1,283 @@
+"""Parity of the HIP library against the CPU oracle (needs an MI355X).
+
+Every comparison uses the same seeded inputs on both sides; expected values
+come only from the oracle.  Tolerances:
+  fp64 paths            1e-12 relative (log pi; normwise per chain for vectors)
+  fp32 VALU path        1e-5
+  bf16 split paths      leapfrog positions/momenta 1e-5 normwise per chain;
+                        log pi 1e-5 relative; gradient 1e-5 (BF16X5) and 5e-5
+                        (BF16X3, whose two-term theta carries ~2^-17 relative
+                        error into eta and from there into the residuals)
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import closed_form, diagnostics, folds, hmc, model, philox, sampler
+from paper_2310_07002_amd import binding, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PREC = {"fp64": W.PREC_FP64, "fp32": W.PREC_FP32, "bf16x3": W.PREC_BF16X3, "bf16x5": W.PREC_BF16X5,
+        "fp64u": W.PREC_FP64_UNFUSED}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _normwise(a, b):
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
+def _oracle_eval(w, theta):
+    roles = folds.roles_of(w)
+    foc = np.arange(w.C) // w.L
+    return (model.log_density(w, theta, roles, foc), model.grad_log_density(w, theta, roles, foc))
+
+
+def _theta_near_init(w, scale=0.3, seed=0):
+    rng = np.random.default_rng(seed)
+    return w.init_pos + scale * np.sqrt(w.inv_mass)[None, :] * rng.standard_normal(w.init_pos.shape)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+# ---------------------------------------------------------------- random streams
+
+def test_philox_bit_exact(dev):
+    for seed, ctr in [(0, (0, 0, 0, 0)), (0xFFFFFFFFFFFFFFFF, (0xFFFFFFFF,) * 4),
+                      (0x299F31D0A4093822, (0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344)),
+                      (20231007 * 10 + 2, (7, 123, 1, 0))]:
+        got = binding.pcv_philox(seed, *ctr, 64)
+        k = philox.seed_key(seed)
+        want = np.stack([np.asarray(x, dtype=np.uint64) for x in philox.philox4x32_10(
+            (np.uint64(ctr[0]), np.uint64(ctr[1]), np.uint64(ctr[2]),
+             (np.uint64(ctr[3]) + np.arange(64, dtype=np.uint64)) & np.uint64(0xFFFFFFFF)), k)], axis=1)
+        np.testing.assert_array_equal(got.astype(np.uint64), want)
+
+
+# ---------------------------------------------------------------- value and gradient
+
+CASES = [
+    ("c1", "fp64", None, 1e-12, 1e-12),
+    ("c3", "fp64", (0, 40), 1e-12, 1e-12),
+    ("c2", "fp32", None, 1e-5, 1e-5),
+    ("c4", "fp64u", (0, 16), 1e-12, 1e-12),
+    ("c4", "bf16x5", (0, 16), 1e-5, 1e-5),
+    ("c4", "bf16x3", (0, 16), 1e-5, 5e-5),
+    ("c4", "fp32", (0, 16), 1e-5, 1e-5),
+    ("c5", "bf16x5", (100, 140), 1e-5, 1e-5),
+    ("c5", "bf16x3", (100, 140), 1e-5, 5e-5),
+]
+
+
+@pytest.mark.parametrize("name,prec,folds_,tol_v,tol_g", CASES)
+def test_logdensity_grad_matches_oracle(dev, name, prec, folds_, tol_v, tol_g):
+    w = W.make(name)
+    if folds_:
+        w = W.fold_subset(w, *folds_)
+    _say(f"[logdensity] {name} {prec} C={w.C}")
+    theta = _theta_near_init(w)
+    lp_o, g_o = _oracle_eval(w, theta)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    rel_v = np.abs(lp - lp_o) / np.abs(lp_o)
+    rel_g = _normwise(g, g_o)
+    _say(f"    logp rel max {rel_v.max():.2e}  grad normwise max {rel_g.max():.2e} median {np.median(rel_g):.2e}")
+    assert rel_v.max() < tol_v
+    assert rel_g.max() < tol_g
+
+
+def test_ragged_chain_tile_and_row_tail(dev):
+    """C not a multiple of the 256-chain tile, n not a multiple of the 32-row tile."""
+    w = W.fold_subset(W.make("c4"), 3, 40)          # 296 chains
+    w = dataclasses.replace(w, X=w.X[:19990], y=w.y[:19990], fold_index=w.fold_index[:19990])
+    _say(f"[ragged] C={w.C} n={w.n}")
+    theta = _theta_near_init(w, seed=3)
+    lp_o, g_o = _oracle_eval(w, theta)
+    s = binding.PCV.from_workload(w, precision=W.PREC_BF16X5)
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    assert (np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)).max() < 1e-5
+    assert _normwise(g.cpu().numpy(), g_o).max() < 1e-5
+
+
+def test_dense_fold_encoding_matches_index(dev):
+    w = W.fold_subset(W.make("c1"), 0, 30)
+    wd = W.with_dense_roles(w)
+    theta = _theta_near_init(w, seed=4)
+    t = torch.tensor(theta, device=dev)
+    lp1, g1 = binding.PCV.from_workload(w).logdensity_grad(t)
+    lp2, g2 = binding.PCV.from_workload(wd).logdensity_grad(t)
+    np.testing.assert_allclose(lp2.cpu().numpy(), lp1.cpu().numpy(), rtol=1e-14)
+    np.testing.assert_allclose(g2.cpu().numpy(), g1.cpu().numpy(), rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- single leapfrog trajectories
+
+@pytest.mark.parametrize("name,prec,folds_,tol", [("c1", "fp64", None, 1e-12), ("c3", "fp64", (0, 30), 1e-12),
+                                                 ("c4", "bf16x3", (0, 16), 1e-5),
+                                                 ("c5", "bf16x3", (0, 32), 1e-5),
+                                                 ("c5", "bf16x5", (0, 32), 1e-5)])
+@pytest.mark.parametrize("n_steps", [1, 8])
+def test_leapfrog_matches_oracle(dev, name, prec, folds_, tol, n_steps):
+    """One step at the stated tolerance.  Over a whole 8-step trajectory the
+    BF16X3 gradient error (~2e-5 normwise) enters the momentum once per step,
+    so its bound there is 2e-5."""
+    if prec == "bf16x3" and n_steps > 1:
+        tol = 2e-5
+    w = W.make(name)
+    if folds_:
+        w = W.fold_subset(w, *folds_)
+    _say(f"[leapfrog] {name} {prec} steps={n_steps}")
+    roles = folds.roles_of(w)
+    foc = np.arange(w.C) // w.L
+    q0 = _theta_near_init(w, seed=5)
+    p0 = philox.momentum_normals(w.seed, w.chain_offset + np.arange(w.C), 0, w.d) / np.sqrt(w.inv_mass)
+    g0 = model.grad_log_density(w, q0, roles, foc)
+    q1, p1, g1, lp1 = hmc.leapfrog(w, q0, p0, g0, n_steps, w.step_size, roles, foc)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    qg, pg, lpg, gg = s.leapfrog(torch.tensor(q0, device=dev), torch.tensor(p0, device=dev), n_steps)
+    eq = _normwise(qg.cpu().numpy(), q1)
+    ep = _normwise(pg.cpu().numpy(), p1)
+    ev = np.abs(lpg.cpu().numpy() - lp1) / np.abs(lp1)
+    _say(f"    q {eq.max():.2e}  p {ep.max():.2e}  logp {ev.max():.2e}")
+    assert eq.max() < tol and ep.max() < tol and ev.max() < tol
+
+
+# ---------------------------------------------------------------- whole runs
+
+def _replay(w, n_iter, dev, prec=None):
+    run = sampler.run_all(w, n_iter=n_iter)
+    s = binding.PCV.from_workload(w, precision=prec)
+    s.step(n_iter)
+    return run, s
+
+
+def test_fp64_run_replays_oracle_c1(dev):
+    w = dataclasses.replace(W.make("c1"), n_warmup=100)
+    _say("[replay] c1 fp64 300 iterations")
+    run, s = _replay(w, 300, dev)
+    th, lp, sv = s.get_state()
+    np.testing.assert_allclose(th, run.state.q, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(sv, run.state.s, rtol=1e-9, atol=1e-10)
+    acc = s.get_accumulators(w.n_blocks)
+    np.testing.assert_array_equal(acc["n_accept"], run.acc.n_accept)
+    for k in ("Z", "U", "U2", "V", "V2"):
+        np.testing.assert_allclose(acc[k], getattr(run.acc, k), rtol=1e-9, err_msg=k)
+    np.testing.assert_allclose(acc["blk_mean"], run.acc.blk_mean, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(acc["blk_m2"], run.acc.blk_m2, rtol=1e-8, atol=1e-9)
+    # diagnostics from the device accumulators vs the oracle's own
+    d = s.diagnostics()
+    o = diagnostics.from_accumulators(run.acc, w.K, w.L, w.batch_size)
+    assert abs(d["elpd"] - o["elpd"]) < 1e-9 * abs(o["elpd"])
+    assert abs(d["rhat_max"] - o["rhat_max"]) < 1e-9
+    assert abs(d["mcse"] - o["mcse"]) < 1e-8 * o["mcse"]
+    assert abs(d["ess"] - o["ess"]) < 1e-8 * o["ess"]
+    np.testing.assert_allclose(d["rhat_fold"], o["rhat_fold"], rtol=1e-9)
+    np.testing.assert_allclose(d["ess_fold"], o["ess_fold"], rtol=1e-7)
+    e = s.elpd()
+    np.testing.assert_allclose(e["elpd_fold"], o["elpd_fold"], rtol=1e-10)
+    np.testing.assert_allclose(e["mcse_fold"], o["mcse_fold"], rtol=1e-7)
+    assert d["accept_rate"] == pytest.approx(o["accept_rate"], rel=1e-12)
+    rep_g = s.shuffle_benchmark(20, seed=17)
+    _, rep_o = diagnostics.shuffle_benchmark(run.acc, w.K, w.L, w.n_blocks, 20, seed=17)
+    np.testing.assert_allclose(rep_g, rep_o, rtol=1e-9)
+
+
+def test_fp64_run_replays_oracle_hvblock(dev):
+    w = dataclasses.replace(W.fold_subset(W.make("c3"), 0, 25), n_warmup=40)
+    _say("[replay] c3 fp64 subset 120 iterations")
+    run, s = _replay(w, 120, dev)
+    th, lp, sv = s.get_state()
+    np.testing.assert_allclose(th, run.state.q, rtol=1e-9, atol=1e-10)
+    acc = s.get_accumulators(w.n_blocks)
+    np.testing.assert_array_equal(acc["n_accept"], run.acc.n_accept)
+    np.testing.assert_allclose(acc["U"], run.acc.U, rtol=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x5"])
+def test_bf16_run_tracks_oracle_c5(dev, prec):
+    """Split-precision transitions: accept decisions may differ where the
+    energy error decides; every other chain must track the fp64 oracle."""
+    w = dataclasses.replace(W.fold_subset(W.make("c5"), 0, 32), n_warmup=2)
+    _say(f"[replay] c5 {prec} subset 4 iterations")
+    run, s = _replay(w, 4, dev, prec=PREC[prec])
+    th, lp, sv = s.get_state()
+    err = _normwise(th, run.state.q)
+    acc = s.get_accumulators(w.n_blocks)
+    same = acc["n_accept"] == run.acc.n_accept
+    _say(f"    same decisions {same.mean():.3f}  max err (same) {err[same].max():.2e}")
+    assert same.mean() > 0.97
+    assert err[same].max() < 1e-5
+
+
+def test_hier_fp32_run_tracks_oracle(dev):
+    w = dataclasses.replace(W.make("c2"), n_warmup=2)
+    w = W.fold_subset(w, 0, 10)
+    _say("[replay] c2 fp32 subset 4 iterations")
+    run, s = _replay(w, 4, dev)
+    th, lp, sv = s.get_state()
+    err = _normwise(th, run.state.q)
+    acc = s.get_accumulators(w.n_blocks)
+    same = acc["n_accept"] == run.acc.n_accept
+    _say(f"    same decisions {same.mean():.3f}  max err (same) {err[same].max():.2e}")
+    assert same.mean() > 0.95
+    assert err[same].max() < 1e-4
+
+
+def test_loo_elpd_within_mcse_of_closed_form(dev):
+    """Full first configuration on the device: elpd within 4 MCSE of the exact LOO."""
+    w = W.make("c1")
+    s = binding.PCV.from_workload(w)
+    s.step(w.n_iter)
+    d = s.diagnostics()
+    roles = folds.roles_of(w)
+    exact = sum(closed_form.fold_exact(w.X, w.y, w.sigma, w.prior_scale, roles[k] == 1, roles[k] == 2)["elpd"]
+                for k in range(w.K))
+    _say(f"[c1 full] elpd {d['elpd']:.4f} exact {exact:.4f} mcse {d['mcse']:.4f} rhat_max {d['rhat_max']:.4f}")
+    assert abs(d["elpd"] - exact) < 4 * d["mcse"]
+    assert d["n_draws"] == w.n_samples
+
+
+def test_autograd_function_matches_finite_differences(dev):
+    from paper_2310_07002_amd.autograd import log_density
+    w = W.fold_subset(W.make("c4"), 0, 4)
+    s = binding.PCV.from_workload(w, precision=W.PREC_FP64_UNFUSED)
+    theta = torch.tensor(_theta_near_init(w, seed=9), device=dev, requires_grad=True)
+    weights = torch.linspace(0.5, 1.5, w.C, dtype=torch.float64, device=dev)
+    (log_density(theta, s) * weights).sum().backward()
+    g = theta.grad.cpu().numpy()
+    h = 1e-6
+    th = theta.detach().cpu().numpy()
+    rng = np.random.default_rng(1)
+    for j in rng.choice(w.d, size=6, replace=False):
+        e = np.zeros_like(th)
+        e[:, j] = h
+        lp_p, _ = s.logdensity_grad(torch.tensor(th + e, device=dev), want_grad=False)
+        lp_m, _ = s.logdensity_grad(torch.tensor(th - e, device=dev), want_grad=False)
+        fd = (lp_p - lp_m).cpu().numpy() / (2 * h) * weights.cpu().numpy()
+        np.testing.assert_allclose(g[:, j], fd, rtol=2e-5, atol=2e-4)
+
+
+def test_state_roundtrip_and_divergence_counting(dev):
+    w = dataclasses.replace(W.fold_subset(W.make("c1"), 0, 8), n_warmup=0, step_size=5.0)
+    s = binding.PCV.from_workload(w)
+    th0, lp0, s0 = s.get_state()
+    np.testing.assert_allclose(th0, w.init_pos, rtol=0, atol=0)
+    s.step(10)
+    d = s.diagnostics()
+    assert d["n_divergent"] > 0
+    s.set_state(w.init_pos)
+    th1, lp1, s1 = s.get_state()
+    np.testing.assert_array_equal(th1, th0)
+    np.testing.assert_allclose(lp1, lp0, rtol=1e-15)
