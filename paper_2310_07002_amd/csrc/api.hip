@@ -378,6 +378,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     ctx->fwd = md->precision == PCV_PREC_BF16X5 ? 5 : 3;
     if (hier) return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path supports the GLM families");
     if (p != 64 && p != 128) return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path supports p = 64 or 128");
+    if (fm->kind == PCV_FOLDS_DENSE)
+      return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path takes index or interval fold encodings");
   } else {
     ctx->path = PATH_UNFUSED;
     if (hier) return fail(ctx, PCV_ERR_UNSUPPORTED, "unfused fp64 path supports the GLM families");

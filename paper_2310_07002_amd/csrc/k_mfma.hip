@@ -47,7 +47,28 @@ struct MfmaArgs {
 
 __device__ __forceinline__ __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
 
-template <int FAM, int P, int FWD, bool VALUE>
+// Residual dl/deta and (optionally) l(y, eta) without its row constant, in
+// fp32 with hardware exp/log/rcp (errors ~1e-7 relative, far below the bf16
+// split error of eta itself).
+template <int FAM>
+__device__ __forceinline__ float mf_resid(float y, float e, float is2) {
+  if (FAM == FAM_GAUSS) return (y - e) * is2;
+  if (FAM == FAM_POIS) return y - __expf(e);
+  return y - __builtin_amdgcn_rcpf(1.0f + __expf(-e));
+}
+template <int FAM>
+__device__ __forceinline__ float mf_ell0(float y, float e, float is2) {
+  if (FAM == FAM_GAUSS) {
+    const float d = y - e;
+    return -0.5f * d * d * is2;
+  }
+  if (FAM == FAM_POIS) return y * e - __expf(e);
+  const float t = __expf(-fabsf(e));                       // in (0, 1]
+  const float l1p = t > 1e-4f ? __logf(1.0f + t) : t * (1.0f - 0.5f * t);
+  return y * e - (fmaxf(e, 0.0f) + l1p);
+}
+
+template <int FAM, int P, int FWD, bool VALUE, int FK>
 __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   constexpr int KB = P / 32;
   constexpr int MB = P / 16;
@@ -55,11 +76,13 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   constexpr int NF = mf_nfrag(P);
   constexpr int NST = NF * 64 / (64 * MF_WAVES);  // uint4 staged per thread
   constexpr int NT = FWD == 5 ? 3 : 2;             // theta terms
+  constexpr int NBUF = 4;                          // LDS ring of row tiles
   static_assert(NST * 64 * MF_WAVES == NF * 64, "staging must tile the fragments");
+  static_assert(NST == 2 || NST == 4, "two or four staged vectors per thread");
 
-  __shared__ __align__(16) uint4 sfrag[NF * 64];
-  __shared__ float sy[MF_ROWS];
-  __shared__ int32_t sf[MF_ROWS];
+  __shared__ __align__(16) uint4 sfrag[NBUF][NF * 64];
+  __shared__ float sy[NBUF][MF_ROWS];
+  __shared__ int32_t sf[NBUF][MF_ROWS];
 
   const DevModel& m = a.m;
   const int tid = threadIdx.x;
@@ -73,6 +96,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   const bool wave_active = cbase < m.C;
   const int t_beg = sp * a.tiles_per_split;
   const int t_end = min(a.n_tiles, t_beg + a.tiles_per_split);
+  const int t_last = t_end > t_beg ? t_end - 1 : t_beg;
 
   // chains of this lane in its two 16-chain blocks
   int kf[2], elo[2], ehi[2];
@@ -85,7 +109,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
     kf[cb] = static_cast<int>(cc / m.L);
     elo[cb] = 0;
     ehi[cb] = 0;
-    if (m.fold_kind == PCV_FOLDS_INTERVALS) {
+    if (FK == PCV_FOLDS_INTERVALS) {
       elo[cb] = m.ivals[4 * kf[cb] + 2];
       ehi[cb] = m.ivals[4 * kf[cb] + 3];
     }
@@ -129,59 +153,36 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   double vacc[2] = {0.0, 0.0};
   const float is2 = static_cast<float>(m.inv_sigma2);
 
-  // register staging of the next tile (the clamped index keeps the last,
-  // redundant prefetch inside the buffer)
-  static_assert(NST == 2 || NST == 4, "two or four staged vectors per thread");
+  // ---- staging: global -> registers -> LDS ring ---------------------------
   uint4 st0, st1, st2, st3;   // named registers: a private array here ends up in scratch
   float my_y = 0.f;
   int32_t my_f = 0;
-  const int t_last = t_end > t_beg ? t_end - 1 : t_beg;
-  {
-    const int tt0 = min(t_beg, a.n_tiles - 1);
-    const uint4* src = a.Xpk + static_cast<int64_t>(tt0) * NF * 64;
+  auto load_stage = [&](int tt) {
+    const uint4* src = a.Xpk + static_cast<int64_t>(tt) * NF * 64;
     st0 = src[tid];
     st1 = src[512 + tid];
     if constexpr (NST == 4) {
       st2 = src[1024 + tid];
       st3 = src[1536 + tid];
     }
-    if (tid < MF_ROWS) {
-      my_y = a.ty[static_cast<int64_t>(tt0) * MF_ROWS + tid];
-      my_f = a.tfid[static_cast<int64_t>(tt0) * MF_ROWS + tid];
-    }
-  }
-
-  for (int tt = t_beg; tt < t_end; ++tt) {
-    __syncthreads();
-    sfrag[tid] = st0;
-    sfrag[512 + tid] = st1;
+    // every thread carries the metadata of row (tid mod 32): duplicate stores
+    // of equal values keep the loop body free of branches
+    my_y = a.ty[static_cast<int64_t>(tt) * MF_ROWS + (tid & (MF_ROWS - 1))];
+    my_f = a.tfid[static_cast<int64_t>(tt) * MF_ROWS + (tid & (MF_ROWS - 1))];
+  };
+  auto store_stage = [&](int b) {
+    sfrag[b][tid] = st0;
+    sfrag[b][512 + tid] = st1;
     if constexpr (NST == 4) {
-      sfrag[1024 + tid] = st2;
-      sfrag[1536 + tid] = st3;
+      sfrag[b][1024 + tid] = st2;
+      sfrag[b][1536 + tid] = st3;
     }
-    if (tid < MF_ROWS) {
-      sy[tid] = my_y;
-      sf[tid] = my_f;
-    }
-    __syncthreads();
-    {
-      const int tn = min(tt + 1, t_last);
-      const uint4* src = a.Xpk + static_cast<int64_t>(tn) * NF * 64;
-      st0 = src[tid];
-      st1 = src[512 + tid];
-      if constexpr (NST == 4) {
-        st2 = src[1024 + tid];
-        st3 = src[1536 + tid];
-      }
-      if (tid < MF_ROWS) {
-        my_y = a.ty[static_cast<int64_t>(tn) * MF_ROWS + tid];
-        my_f = a.tfid[static_cast<int64_t>(tn) * MF_ROWS + tid];
-      }
-    }
-    if (!wave_active) continue;
+    sy[b][tid & (MF_ROWS - 1)] = my_y;
+    sf[b][tid & (MF_ROWS - 1)] = my_f;
+  };
 
-    // ---- forward: eta[32 rows x 32 chains] -------------------------------
-    f32x4 eta[2][2];
+  // forward product of one tile (buffer b): eta[32 rows x 32 chains]
+  auto forward = [&](int b, f32x4 (&eta)[2][2]) {
 #pragma unroll
     for (int mh = 0; mh < 2; ++mh)
 #pragma unroll
@@ -191,8 +192,8 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
 #pragma unroll
       for (int mh = 0; mh < 2; ++mh) {
         const int f = (mh * KB + kb) * 2;
-        const bf16x8 x0 = __builtin_bit_cast(bf16x8, sfrag[f * 64 + lane]);
-        const bf16x8 x1 = __builtin_bit_cast(bf16x8, sfrag[(f + 1) * 64 + lane]);
+        const bf16x8 x0 = __builtin_bit_cast(bf16x8, sfrag[b][f * 64 + lane]);
+        const bf16x8 x1 = __builtin_bit_cast(bf16x8, sfrag[b][(f + 1) * 64 + lane]);
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
           f32x4 acc = eta[mh][cb];
@@ -207,48 +208,160 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
         }
       }
     }
+  };
 
-    // ---- epilogue: masked residual, split into bf16 hi/lo ----------------
-    bf16x8 rhi[2], rlo[2];
+  // The per-tile work is cut into NG groups that alternate between the
+  // forward product of the next tile (group 2q: K block q/2.. of M half) and
+  // the adjoint product of the previous tile (group 2q+1: M block q), each
+  // group = two fragment reads + 6 (or 10) MFMAs, with EPG epilogue
+  // elements of the current tile in between.  The three streams are
+  // independent, so the order is pinned with scheduling barriers.
+  constexpr int NG = 2 * MB;            // = 2 * (2 * KB)
+  constexpr int EPG = 16 / NG;          // epilogue elements per group
+  static_assert(EPG * NG == 16, "16 epilogue elements per lane per tile");
+
+  auto frag = [&](int b, int f) { return __builtin_bit_cast(bf16x8, sfrag[b][f * 64 + lane]); };
+  auto group_frag_index = [&](int g) {
+    // forward groups (even g): (mh, kb) = ((g/2) / KB, (g/2) % KB); adjoint groups (odd g): mb = g/2
+    return (g & 1) ? NFF + (g >> 1) * 2 : (((g >> 1) / KB) * KB + ((g >> 1) % KB)) * 2;
+  };
+
+  // Skewed software pipeline over row tiles: iteration tt issues
+  // forward(tt+1), adjoint(tt-1) and epilogue(tt).  Ring slot of tile tt is
+  // (tt - t_beg) mod 4: slots hold tt-1, tt, tt+1 and receive tt+2.
+  // Prologue: tile t_beg into slots 0 and 3 (slot 3 stands in for "tile
+  // t_beg-1", whose adjoint runs with zero residuals), t_beg+1 into slot 1.
+  load_stage(t_beg < t_last ? t_beg : t_last);
+  store_stage(0);
+  store_stage(3);
+  load_stage(min(t_beg + 1, t_last));
+  store_stage(1);
+  load_stage(min(t_beg + 2, t_last));
+  __syncthreads();
+  f32x4 eta_cur[2][2], eta_nxt[2][2];
+  forward(0, eta_cur);
+  bf16x8 rph[2], rpl[2], rch[2], rcl[2];   // residual fragments: previous / current tile
 #pragma unroll
-    for (int mh = 0; mh < 2; ++mh) {
+  for (int cb = 0; cb < 2; ++cb) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int rl = mh * 16 + 4 * g4 + i;
-        const int64_t row = static_cast<int64_t>(tt) * MF_ROWS + rl;
-        const float y = sy[rl];
-        const int fr = sf[rl];
-        const bool rv = row < m.n;
+    for (int e = 0; e < 8; ++e) {
+      rph[cb][e] = to_bf16(0.f);
+      rpl[cb][e] = to_bf16(0.f);
+    }
+  }
+
+  for (int tt = t_beg; tt < t_end; ++tt) {
+    const int i = tt - t_beg;
+    const int bc = i & 3, b1 = (i + 1) & 3, b2 = (i + 2) & 3, bp = (i + 3) & 3;
+    // all waves are done with iteration tt-1; tile tt+1 (stored then) is visible
+    __syncthreads();
+    store_stage(b2);
+    load_stage(min(tt + 3, t_last));
+    // (a wave whose chains are all past C computes on clamped chains and
+    // discards the result: no branch in the loop body)
+
+    // metadata of the 8 rows this lane sees in tile tt
+    float yr[8];
+    int fr8[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int rl = (e >> 2) * 16 + 4 * g4 + (e & 3);
+      yr[e] = sy[bc][rl];
+      fr8[e] = sf[bc][rl];
+    }
+#pragma unroll
+    for (int mh = 0; mh < 2; ++mh)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) eta_nxt[mh][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float vt[2] = {0.f, 0.f};
+
+    bf16x8 xa0 = frag(b1, group_frag_index(0)), xa1 = frag(b1, group_frag_index(0) + 1);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      // prefetch the next group's fragments
+      bf16x8 xb0 = xa0, xb1 = xa1;
+      if (g + 1 < NG) {
+        const int bn = ((g + 1) & 1) ? bp : b1;
+        xb0 = frag(bn, group_frag_index(g + 1));
+        xb1 = frag(bn, group_frag_index(g + 1) + 1);
+      }
+      if ((g & 1) == 0) {
+        const int q = g >> 1, mh = q / KB, kb = q % KB;
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
-          bool train;
-          if (m.fold_kind == PCV_FOLDS_INDEX) train = rv && (fr != kf[cb]);
-          else if (m.fold_kind == PCV_FOLDS_INTERVALS) train = rv && ((row < elo[cb]) || (row >= ehi[cb]));
-          else train = rv && (m.roles[static_cast<int64_t>(kf[cb]) * m.n + row] == 1);
-          const float e = eta[mh][cb][i];
-          const float r = train ? resid32<FAM>(y, e, is2) : 0.f;
-          if (VALUE) {
-            if (train) vacc[cb] += static_cast<double>(ell0_32<FAM>(y, e, is2));
+          f32x4 acc = eta_nxt[mh][cb];
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, th[0][kb][cb], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, th[1][kb][cb], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa1, th[0][kb][cb], acc, 0, 0, 0);
+          if (NT == 3) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, th[NT - 1][kb][cb], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa1, th[1][kb][cb], acc, 0, 0, 0);
           }
-          const __bf16 h = to_bf16(r);
-          rhi[cb][mh * 4 + i] = h;
-          rlo[cb][mh * 4 + i] = to_bf16(r - static_cast<float>(h));
+          eta_nxt[mh][cb] = acc;
+        }
+      } else {
+        const int mb = g >> 1;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          f32x4 acc = gacc[mb][cb];
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, rph[cb], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, rpl[cb], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa1, rph[cb], acc, 0, 0, 0);
+          gacc[mb][cb] = acc;
         }
       }
+      // epilogue elements of tile tt: element index el -> (row slot e, chain block cb)
+#pragma unroll
+      for (int u = 0; u < EPG; ++u) {
+        const int el = g * EPG + u;
+        const int e = el >> 1, cb = el & 1;
+        const int mh = e >> 2, ii = e & 3;
+        const int row = tt * MF_ROWS + mh * 16 + 4 * g4 + ii;
+        const bool rv = row < m.n;
+        bool train;
+        if (FK == PCV_FOLDS_INDEX) train = rv & (fr8[e] != kf[cb]);
+        else train = rv & ((row < elo[cb]) | (row >= ehi[cb]));
+        const float x = eta_cur[mh][cb][ii];
+        const float rr = mf_resid<FAM>(yr[e], x, is2);
+        const float r = train ? rr : 0.f;
+        if (VALUE) {
+          const float l0 = mf_ell0<FAM>(yr[e], x, is2);
+          vt[cb] += train ? l0 : 0.f;
+        }
+        const __bf16 h = to_bf16(r);
+        rch[cb][e] = h;
+        rcl[cb][e] = to_bf16(r - static_cast<float>(h));
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      xa0 = xb0;
+      xa1 = xb1;
     }
-
-    // ---- adjoint: G[P x 32 chains] += X' R ------------------------------
+    if (VALUE) {
+      vacc[0] += static_cast<double>(vt[0]);
+      vacc[1] += static_cast<double>(vt[1]);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      rph[cb] = rch[cb];
+      rpl[cb] = rcl[cb];
+    }
+#pragma unroll
+    for (int mh = 0; mh < 2; ++mh)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) eta_cur[mh][cb] = eta_nxt[mh][cb];
+  }
+  // adjoint of the last tile (its slot is untouched since it was loaded)
+  {
+    const int bl = (t_end - 1 - t_beg) & 3;
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      const int f = NFF + mb * 2;
-      const bf16x8 x0 = __builtin_bit_cast(bf16x8, sfrag[f * 64 + lane]);
-      const bf16x8 x1 = __builtin_bit_cast(bf16x8, sfrag[(f + 1) * 64 + lane]);
+      const bf16x8 x0 = frag(bl, NFF + mb * 2), x1 = frag(bl, NFF + mb * 2 + 1);
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
         f32x4 acc = gacc[mb][cb];
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, rhi[cb], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, rlo[cb], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, rhi[cb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, rph[cb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, rpl[cb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, rph[cb], acc, 0, 0, 0);
         gacc[mb][cb] = acc;
       }
     }
@@ -263,9 +376,9 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int j = mb * 16 + 4 * g4 + i;
-          a.Gpart[(static_cast<int64_t>(sp) * P + j) * m.C + c] = gacc[mb][cb][i];
+        for (int ii = 0; ii < 4; ++ii) {
+          const int j = mb * 16 + 4 * g4 + ii;
+          a.Gpart[(static_cast<int64_t>(sp) * P + j) * m.C + c] = gacc[mb][cb][ii];
         }
     }
     if (VALUE) {
@@ -318,8 +431,14 @@ __global__ void k_mfma_pack(const double* __restrict__ X, int64_t n, int P, int 
 
 template <int FAM, int P, int FWD>
 static hipError_t launch_mfma_p(const MfmaArgs& a, bool value, int nblk, hipStream_t st) {
-  if (value) hipLaunchKernelGGL((k_mfma<FAM, P, FWD, true>), dim3(nblk), dim3(512), 0, st, a);
-  else hipLaunchKernelGGL((k_mfma<FAM, P, FWD, false>), dim3(nblk), dim3(512), 0, st, a);
+  const bool iv = a.m.fold_kind == PCV_FOLDS_INTERVALS;
+  if (value) {
+    if (iv) hipLaunchKernelGGL((k_mfma<FAM, P, FWD, true, PCV_FOLDS_INTERVALS>), dim3(nblk), dim3(512), 0, st, a);
+    else hipLaunchKernelGGL((k_mfma<FAM, P, FWD, true, PCV_FOLDS_INDEX>), dim3(nblk), dim3(512), 0, st, a);
+  } else {
+    if (iv) hipLaunchKernelGGL((k_mfma<FAM, P, FWD, false, PCV_FOLDS_INTERVALS>), dim3(nblk), dim3(512), 0, st, a);
+    else hipLaunchKernelGGL((k_mfma<FAM, P, FWD, false, PCV_FOLDS_INDEX>), dim3(nblk), dim3(512), 0, st, a);
+  }
   return hipGetLastError();
 }
 
