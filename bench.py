@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--no-plain-fp64", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--time-to-rhat", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 512 MiB device-to-device copy first (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -116,6 +118,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prec = args.precision or DEFAULT_PREC[args.workload]
     log(f"bench: generating workload {args.workload}")
     w = W.make(args.workload)
@@ -157,8 +165,9 @@ def main():
                 "alg_flops_per_launch": flops_per_launch, "mean_launch_ms": avg_s * 1e3,
                 "launches": k_n}
     if prec.startswith("bf16"):
-        nprod = 6 if prec == "bf16x3" else 8
-        roofline["issued_mfma_frac"] = achieved * nprod / 4.0 / peak if achieved else None
+        # issued bf16 products per algorithmic product: (forward terms + 3 adjoint terms) / 2
+        ratio = (3 + 3) / 2 if prec == "bf16x3" else (5 + 3) / 2
+        roofline["issued_mfma_frac"] = achieved * ratio / peak if achieved else None
 
     line = {"metric": "gradient evals/sec over all fold×chain states", "value": value,
             "unit": "gradient evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

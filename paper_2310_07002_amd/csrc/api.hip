@@ -537,12 +537,26 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     const int R = mfma_rows_per_tile();
     ctx->n_tiles = static_cast<int>((n + R - 1) / R);
     const int n_ct = static_cast<int>((C + mfma_chain_tile() - 1) / mfma_chain_tile());
-    // splits: enough workgroups to fill the chip several times over, each with
-    // a useful number of row tiles
+    // Row splits per chain tile.  One workgroup fits per CU (LDS ring and
+    // registers), so workgroups run in rounds of 256; a task costs its tiles
+    // plus about four tiles of pipeline fill and partial-result traffic.
+    // Pick the split count with the smallest estimated time.
     int ns = 1;
-    while (static_cast<int64_t>(n_ct) * ns < 4 * 256 && ctx->n_tiles / (ns + 1) >= 8) ++ns;
+    double best = 1e300;
+    for (int cand = 1; cand <= 64 && cand <= ctx->n_tiles; ++cand) {
+      const int64_t tasks = static_cast<int64_t>(n_ct) * cand;
+      const double rounds = static_cast<double>((tasks + 255) / 256);
+      const double per_task = std::ceil(static_cast<double>(ctx->n_tiles) / cand) + 4.0;
+      const double cost = rounds * per_task;
+      if (cost < best - 1e-9) {
+        best = cost;
+        ns = cand;
+      }
+    }
     ctx->tiles_per_split = (ctx->n_tiles + ns - 1) / ns;
     ctx->n_splits = (ctx->n_tiles + ctx->tiles_per_split - 1) / ctx->tiles_per_split;
+    if (ctx->tiles_per_split < 1 || static_cast<int64_t>(ctx->n_splits) * ctx->tiles_per_split < ctx->n_tiles)
+      return fail(ctx, PCV_ERR_DEVICE, "internal error: row splits do not cover the rows");
     const size_t nfr = static_cast<size_t>(ctx->n_tiles) * mfma_nfrag(static_cast<int>(p)) * 64;
     TRY(dalloc(ctx, &ctx->Xpk, nfr));
     CK(launch_mfma_pack(X64, n, static_cast<int>(p), ctx->n_tiles, ctx->Xpk, ctx->st));

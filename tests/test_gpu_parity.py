@@ -281,3 +281,27 @@ def test_state_roundtrip_and_divergence_counting(dev):
     th1, lp1, s1 = s.get_state()
     np.testing.assert_array_equal(th1, th0)
     np.testing.assert_allclose(lp1, lp0, rtol=1e-15)
+
+
+@pytest.mark.parametrize("name,prec,tol_g", [("c5", "bf16x3", 5e-5), ("c4", "bf16x3", 5e-5), ("c5", "bf16x5", 1e-5)])
+def test_full_size_sampled_parity(dev, name, prec, tol_g):
+    """The full configuration in the launch shape the benchmark times (all
+    chains, all row splits), checked on sampled folds one at a time."""
+    w = W.make(name)
+    _say(f"[full size] {name} {prec} C={w.C}")
+    theta = _theta_near_init(w, seed=11)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    lp, g = lp.cpu().numpy(), g.cpu().numpy()
+    assert np.all(np.isfinite(lp)) and np.all(np.isfinite(g))
+    rng = np.random.default_rng(5)
+    worst_v = worst_g = 0.0
+    for k in sorted(rng.choice(w.K, size=12, replace=False).tolist()) + [w.K - 1]:
+        sub = W.fold_subset(w, k, k + 1)
+        sl = slice(k * w.L, (k + 1) * w.L)
+        lp_o, g_o = _oracle_eval(sub, theta[sl])
+        worst_v = max(worst_v, float(np.max(np.abs(lp[sl] - lp_o) / np.abs(lp_o))))
+        worst_g = max(worst_g, float(np.max(_normwise(g[sl], g_o))))
+    _say(f"    sampled folds: logp rel max {worst_v:.2e}  grad normwise max {worst_g:.2e}")
+    assert worst_v < 1e-5
+    assert worst_g < tol_g
