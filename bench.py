@@ -83,13 +83,20 @@ def cpu_baseline(w, budget_s=15.0):
 
 
 def traffic_from_profiles(w, prec):
+    """HBM bytes per launch of the gradient kernel from the committed counter
+    summary, or None if there is none or the kernel source changed since the
+    counters were taken."""
+    import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{w.name}_{prec}.json")
-    if not os.path.exists(path):
+    src = os.path.join(ROOT, "paper_2310_07002_amd", "csrc", "k_mfma.hip")
+    if not os.path.exists(path) or not os.path.exists(src):
         return None
     try:
         with open(path) as f:
             t = json.load(f)
-        return t.get("bytes_per_launch")
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        return t.get("bytes_per_launch") if t.get("kernel_source_sha256_16") == h else None
     except Exception:
         return None
 

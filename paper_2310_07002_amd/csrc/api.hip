@@ -43,6 +43,7 @@ hipError_t launch_diag(const DevModel& m, int64_t N, double* fold_buf, double* o
 hipError_t launch_shuffle(const DevModel& m, int64_t N, int R, uint32_t s0, uint32_t s1, double* rep,
                           double* repmax, hipStream_t st);
 hipError_t launch_kick_drift(const DevModel& m, hipStream_t st);
+hipError_t launch_tick(const DevModel& m, hipStream_t st);
 }  // namespace pcv
 
 using namespace pcv;
@@ -76,6 +77,12 @@ struct pcv_ctx_s {
   double* fold_buf = nullptr;
   double* dscal = nullptr;
   double prior_const = 0.0;
+  // captured transition (split paths)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graphs = true;
+  int64_t t_host = 0;   // staging for the device counter upload
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -220,6 +227,8 @@ pcv_status adopt_q1(pcv_ctx ctx) {
   return PCV_OK;
 }
 
+// One transition of the split paths.  t >= 0: explicit iteration number;
+// t < 0: kernels read the device counter, which the last node advances.
 pcv_status transition_split(pcv_ctx ctx, int64_t t) {
   DevModel& m = ctx->m;
   CK(launch_momentum(m, t, ctx->st));
@@ -229,6 +238,36 @@ pcv_status transition_split(pcv_ctx ctx, int64_t t) {
     TRY(split_reduce(ctx, last ? 2 : 1));
   }
   CK(launch_accept(m, ctx->Vpart, split_count(ctx), t, ctx->st));
+  if (t < 0) CK(launch_tick(m, ctx->st));
+  return PCV_OK;
+}
+
+// Capture one transition (device counter mode) into a graph on a private
+// stream; replays are launched on the context stream.  The captured work
+// holds no memset nodes.  The library GEMMs of the unfused path are not
+// captured (that path runs eagerly).
+pcv_status capture_transition(pcv_ctx ctx) {
+  if (ctx->graph_exec) return PCV_OK;
+  if (!ctx->cap_stream) CK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  hipStream_t user = ctx->st;
+  ctx->st = ctx->cap_stream;
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+  pcv_status s = PCV_OK;
+  if (e == hipSuccess) s = transition_split(ctx, -1);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+  ctx->st = user;
+  ctx->timing = timing;
+  if (e != hipSuccess || e2 != hipSuccess || s != PCV_OK || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    ctx->graphs = false;   // fall back to eager launches of the same kernels
+    return PCV_OK;
+  }
+  ctx->graph = g;
+  CK(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
   return PCV_OK;
 }
 
@@ -265,6 +304,9 @@ void pcv_destroy(pcv_ctx ctx) {
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->rb) rocblas_destroy_handle(ctx->rb);
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
 }
 
@@ -484,6 +526,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   TRY(dalloc(ctx, &m.bm2, static_cast<size_t>(m.D) * C));
   TRY(dalloc(ctx, &m.nacc, C));
   TRY(dalloc(ctx, &m.ndiv, C));
+  TRY(dalloc(ctx, &m.t_dev, 1));
   TRY(dalloc(ctx, &ctx->fold_buf, 6 * static_cast<size_t>(K)));
   TRY(dalloc(ctx, &ctx->dscal, 8));
   TRY(dalloc(ctx, &ctx->Vpart, C));
@@ -643,6 +686,19 @@ pcv_status pcv_step(pcv_ctx ctx, int64_t n_iter) {
       timing_end(ctx);
     }
     ctx->t += n_iter;
+    return PCV_OK;
+  }
+  const bool use_graph = ctx->graphs && !ctx->timing && ctx->path == PATH_MFMA && n_iter > 0;
+  if (use_graph) {
+    TRY(capture_transition(ctx));
+  }
+  if (use_graph && ctx->graph_exec) {
+    ctx->t_host = ctx->t;
+    CK(hipMemcpyAsync(ctx->m.t_dev, &ctx->t_host, sizeof(int64_t), hipMemcpyHostToDevice, ctx->st));
+    for (int64_t i = 0; i < n_iter; ++i) CK(hipGraphLaunch(ctx->graph_exec, ctx->st));
+    ctx->t += n_iter;
+    // t_host must stay unchanged until the copy above has run
+    CK(hipStreamSynchronize(ctx->st));
     return PCV_OK;
   }
   for (int64_t i = 0; i < n_iter; ++i) {

@@ -12,7 +12,13 @@ static inline int nblocks(int64_t n, int tpb = TPB) { return static_cast<int>((n
 
 __global__ void k_momentum(DevModel m, int64_t t) {
   const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (t < 0) t = *m.t_dev;
   if (c < m.C) momentum_and_first_drift(m, c, t);
+}
+
+// Advance the device-side transition counter (last node of a captured transition).
+__global__ void k_tick(DevModel m) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *m.t_dev += 1;
 }
 
 // Sum partial gradients over row splits (fixed order), add the prior, and
@@ -45,6 +51,7 @@ template <int FAM>
 __global__ void k_accept(DevModel m, const double* Vpart, int n_splits, int64_t t) {
   const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (c >= m.C) return;
+  if (t < 0) t = *m.t_dev;
   m.logp1[c] = value_finish(m, Vpart, n_splits, c);
   accept_and_accumulate<FAM>(m, c, t);
 }
@@ -330,6 +337,10 @@ __global__ void k_kick_drift(DevModel m) {
 
 hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st) {
   hipLaunchKernelGGL(k_momentum, dim3(nblocks(m.C)), dim3(TPB), 0, st, m, t);
+  return hipGetLastError();
+}
+hipError_t launch_tick(const DevModel& m, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, m);
   return hipGetLastError();
 }
 hipError_t launch_kick_drift(const DevModel& m, hipStream_t st) {

@@ -53,6 +53,9 @@ struct DevModel {
   // accumulators
   double *Z, *U, *U2, *V, *V2, *bmean, *bm2;   // [C], [D][C]
   int64_t *nacc, *ndiv;
+  // device-side transition counter (read when a kernel is given t < 0, so
+  // one captured graph of a transition can be replayed)
+  int64_t* t_dev;
 };
 
 // ----------------------------------------------------------------------------

@@ -305,3 +305,25 @@ def test_full_size_sampled_parity(dev, name, prec, tol_g):
     _say(f"    sampled folds: logp rel max {worst_v:.2e}  grad normwise max {worst_g:.2e}")
     assert worst_v < 1e-5
     assert worst_g < tol_g
+
+
+def test_graph_replay_matches_eager(dev):
+    """Transitions replayed from the captured graph equal eager launches of
+    the same kernels, replay after replay, with eager work in between."""
+    w = dataclasses.replace(W.fold_subset(W.make("c4"), 0, 40), n_warmup=3)
+    g = binding.PCV.from_workload(w, precision=W.PREC_BF16X3)        # graph replays
+    e = binding.PCV.from_workload(w, precision=W.PREC_BF16X3)        # eager (timing on)
+    e.timing_enable(True)
+    for rep in range(4):
+        g.step(2)
+        e.step(2)
+        th_g, lp_g, s_g = g.get_state()
+        th_e, lp_e, s_e = e.get_state()
+        np.testing.assert_array_equal(th_g, th_e)
+        np.testing.assert_array_equal(s_g, s_e)
+        # eager work on the graph context between replays
+        lp, _ = g.logdensity_grad(torch.tensor(th_g, device=dev), want_grad=False)
+        np.testing.assert_allclose(lp.cpu().numpy(), lp_g, rtol=1e-12)
+    ag, ae = g.get_accumulators(w.n_blocks), e.get_accumulators(w.n_blocks)
+    for k in ("U", "U2", "Z", "blk_mean", "blk_m2", "n_accept"):
+        np.testing.assert_array_equal(ag[k], ae[k])
