@@ -66,11 +66,13 @@ class pcv_diag(ctypes.Structure):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load libpcv.so (raises if it has not been built)."""
+def load_library(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libpcv.so from this package (raises if it has not been built).
+    PCV_LIBRARY may name another build of the same library (experiments)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("PCV_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with python -m paper_2310_07002_amd.build")
     lib = ctypes.CDLL(path)

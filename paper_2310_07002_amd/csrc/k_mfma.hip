@@ -45,25 +45,43 @@ struct MfmaArgs {
   int n_tiles, tiles_per_split, n_splits;
 };
 
+constexpr int MF_XCDS = 8;
+// Bijection on [0, nb): the workgroups of XCD x (b % 8 == x, in launch order
+// b / 8) get tasks x*per + min(x, rem) + b/8, a contiguous range per XCD.
+__host__ __device__ constexpr int mf_xcd_task(int b, int nb) {
+  const int per = nb / MF_XCDS, rem = nb % MF_XCDS;
+  const int x = b % MF_XCDS;
+  return x * per + (x < rem ? x : rem) + b / MF_XCDS;
+}
+
 __device__ __forceinline__ __bf16 to_bf16(float x) { return static_cast<__bf16>(x); }
 
 // Residual dl/deta and (optionally) l(y, eta) without its row constant, in
 // fp32 with hardware exp/log/rcp (errors ~1e-7 relative, far below the bf16
 // split error of eta itself).
+// For the logistic and Poisson families the forward product returns
+// e2 = eta * log2(e) (theta is scaled by log2(e) when it is split), so the
+// exponentials are single v_exp_f32 (base 2) instructions.
+constexpr float LOG2E_F = 1.4426950408889634f;
+constexpr double LOG2E_D = 1.4426950408889634;
+constexpr float LN2_F = 0.6931471805599453f;
 template <int FAM>
-__device__ __forceinline__ float mf_resid(float y, float e, float is2) {
-  if (FAM == FAM_GAUSS) return (y - e) * is2;
-  if (FAM == FAM_POIS) return y - __expf(e);
-  return y - __builtin_amdgcn_rcpf(1.0f + __expf(-e));
+__host__ __device__ constexpr double mf_theta_scale() { return FAM == FAM_GAUSS ? 1.0 : LOG2E_D; }
+template <int FAM>
+__device__ __forceinline__ float mf_resid(float y, float e2, float is2) {
+  if (FAM == FAM_GAUSS) return (y - e2) * is2;
+  if (FAM == FAM_POIS) return y - __builtin_amdgcn_exp2f(e2);
+  return y - __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-e2));
 }
 template <int FAM>
-__device__ __forceinline__ float mf_ell0(float y, float e, float is2) {
+__device__ __forceinline__ float mf_ell0(float y, float e2, float is2) {
   if (FAM == FAM_GAUSS) {
-    const float d = y - e;
+    const float d = y - e2;
     return -0.5f * d * d * is2;
   }
-  if (FAM == FAM_POIS) return y * e - __expf(e);
-  const float t = __expf(-fabsf(e));                       // in (0, 1]
+  const float e = e2 * LN2_F;
+  if (FAM == FAM_POIS) return y * e - __builtin_amdgcn_exp2f(e2);
+  const float t = __builtin_amdgcn_exp2f(-fabsf(e2));    // e^{-|eta|} in (0, 1]
   const float l1p = t > 1e-4f ? __logf(1.0f + t) : t * (1.0f - 0.5f * t);
   return y * e - (fmaxf(e, 0.0f) + l1p);
 }
@@ -90,8 +108,14 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g4 = lane >> 4;
   const int l16 = lane & 15;
-  const int ct = blockIdx.x / a.n_splits;
-  const int sp = blockIdx.x - ct * a.n_splits;
+  // Workgroups are dealt round-robin to the 8 XCDs (workgroup b runs on XCD
+  // b % 8).  Renumber so each XCD gets a contiguous range of tasks, and order
+  // tasks split-major: the workgroups resident on one XCD then share a row
+  // split and stream the same X tiles through that XCD's L2 together.
+  const int task = mf_xcd_task(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int n_ct = static_cast<int>((m.C + MF_CHAIN_TILE - 1) / MF_CHAIN_TILE);
+  const int sp = task / n_ct;
+  const int ct = task - sp * n_ct;
   const int64_t cbase = static_cast<int64_t>(ct) * MF_CHAIN_TILE + wave * MF_CHAINS_PER_WAVE;
   const bool wave_active = cbase < m.C;
   const int t_beg = sp * a.tiles_per_split;
@@ -126,7 +150,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int j = kb * 32 + 8 * g4 + e;
-        const double t = cv ? m.q1[static_cast<int64_t>(j) * m.C + c] : 0.0;
+        const double t = cv ? m.q1[static_cast<int64_t>(j) * m.C + c] * mf_theta_scale<FAM>() : 0.0;
         if (NT == 2) {
           const float t32 = static_cast<float>(t);
           const __bf16 h = to_bf16(t32);
@@ -152,6 +176,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
     for (int cb = 0; cb < 2; ++cb) gacc[mb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
   double vacc[2] = {0.0, 0.0};
   const float is2 = static_cast<float>(m.inv_sigma2);
+  const int nrows = static_cast<int>(m.n);
 
   // ---- staging: global -> registers -> LDS ring ---------------------------
   uint4 st0, st1, st2, st3;   // named registers: a private array here ends up in scratch
@@ -317,7 +342,9 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
         const int e = el >> 1, cb = el & 1;
         const int mh = e >> 2, ii = e & 3;
         const int row = tt * MF_ROWS + mh * 16 + 4 * g4 + ii;
-        const bool rv = row < m.n;
+        // padded rows (row >= n) hold X = 0, so they add nothing to G; only
+        // the value needs them masked
+        const bool rv = !VALUE || row < nrows;
         bool train;
         if (FK == PCV_FOLDS_INDEX) train = rv & (fr8[e] != kf[cb]);
         else train = rv & ((row < elo[cb]) | (row >= ehi[cb]));
