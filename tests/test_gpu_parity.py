@@ -111,6 +111,32 @@ def test_ragged_chain_tile_and_row_tail(dev):
     assert _normwise(g.cpu().numpy(), g_o).max() < 1e-5
 
 
+@pytest.mark.parametrize("prec,tol_v,tol_g", [("bf16x3", 1e-5, 5e-5), ("bf16x5", 1e-5, 1e-5)])
+def test_interval_folds_on_matrix_cores(dev, prec, tol_v, tol_g):
+    """hv-block style folds (test block plus a buffer of h rows each side,
+    interval encoding) through the matrix-core path: rows excluded for a
+    chain's fold must drop out of its value and gradient."""
+    w = W.fold_subset(W.make("c5"), 100, 140)
+    h = 7
+    iv = np.zeros((w.K, 4), dtype=np.int64)
+    for k in range(w.K):
+        rows = np.flatnonzero(w.fold_index == k)
+        lo, hi = int(rows.min()), int(rows.max()) + 1
+        assert hi - lo == rows.size               # blocked folds are contiguous
+        iv[k] = (lo, hi, max(0, lo - h), min(w.n, hi + h))
+    w = dataclasses.replace(w, fold_kind=W.FOLDS_INTERVALS, intervals=iv, fold_index=None)
+    _say(f"[intervals] {prec} C={w.C} K={w.K} h={h}")
+    theta = _theta_near_init(w, seed=5)
+    lp_o, g_o = _oracle_eval(w, theta)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    rel_v = np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)
+    rel_g = _normwise(g.cpu().numpy(), g_o)
+    _say(f"    logp rel max {rel_v.max():.2e}  grad normwise max {rel_g.max():.2e}")
+    assert rel_v.max() < tol_v
+    assert rel_g.max() < tol_g
+
+
 def test_dense_fold_encoding_matches_index(dev):
     w = W.fold_subset(W.make("c1"), 0, 30)
     wd = W.with_dense_roles(w)
