@@ -83,10 +83,25 @@ typedef struct pcv_folds {
   const int8_t* roles;         /* DENSE: K*n entries in {0,1,2}                     */
 } pcv_folds;
 
+/* Encoding of X passed to pcv_init. */
+enum {
+  PCV_X_FP64 = 0,        /* n*p fp64, row-major                                      */
+  PCV_X_BF16_HILO = 1    /* two bf16 planes (uint16 bit patterns), hi then lo, each
+                            n*p row-major; the design is hi + lo, summed exactly in
+                            fp64 (a stored split such as the synthetic c4/c5 designs) */
+};
+
+/* How Rhat is accumulated (Section 4.2). */
+enum {
+  PCV_RHAT_WELFORD = 0,       /* per-block Welford mean and M2, Chan-merged           */
+  PCV_RHAT_SHIFTED_SUMS = 1   /* per-block sums of s - C_k and (s - C_k)^2, with C_k
+                                 the fold's warm-up mean of s (Algorithm A2)          */
+};
+
 typedef struct pcv_model {
   int32_t family;              /* PCV_FAMILY_*                                      */
   int32_t precision;           /* PCV_PREC_*                                        */
-  int64_t n, p;                /* X is n x p, row-major, fp64                       */
+  int64_t n, p;                /* X is n x p, row-major (encoding: x_format)        */
   int32_t K, L;                /* folds, chains per fold (L >= 2)                   */
   int32_t n_groups;            /* HIER_LOGISTIC: number of groups                   */
   const int32_t* group_of;     /* HIER_LOGISTIC: n entries in [0, n_groups), sorted */
@@ -105,6 +120,8 @@ typedef struct pcv_model {
                                   to the last block                                  */
   uint64_t seed;               /* Philox4x32-10 key                                  */
   int64_t chain_offset;        /* global id of chain 0 (0 for a full run)            */
+  int32_t x_format;            /* PCV_X_*: encoding of the X argument of pcv_init   */
+  int32_t rhat_mode;           /* PCV_RHAT_*                                         */
 } pcv_model;
 
 typedef struct pcv_diag {
@@ -126,12 +143,13 @@ typedef struct pcv_ctx_s* pcv_ctx;
  * its gradient and the log predictive at the initial positions (Section 3,
  * Steps 2-3: every fold starts from draws of the full-data fit and reuses its
  * step size and mass matrix, Section 3.1).
- * X: n*p row-major fp64; y: n fp64.  Errors: PCV_ERR_INVALID_ARG (n, p, K <= 0;
+ * X: as model->x_format says (n*p row-major fp64, or two bf16 planes); y: n
+ * fp64.  Errors: PCV_ERR_INVALID_ARG (n, p, K <= 0;
  * L < 2; non-finite X, y or init_pos; y outside the family's support; a fold
  * with no test or no training row; step_size, inv_mass, sigma <= 0;
  * n_leapfrog < 1; batch settings < 1), PCV_ERR_UNSUPPORTED, PCV_ERR_NOMEM,
  * PCV_ERR_DEVICE.  *out is NULL on error. */
-pcv_status pcv_init(pcv_ctx* out, const pcv_model* model, const double* X, const double* y,
+pcv_status pcv_init(pcv_ctx* out, const pcv_model* model, const void* X, const double* y,
                     const pcv_folds* fold_masks);
 
 /* Queue all further work of ctx on hip_stream (a hipStream_t; NULL = the
@@ -198,6 +216,22 @@ pcv_status pcv_set_state(pcv_ctx ctx, const double* theta);
 pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, double* V,
                                 double* V2, double* blk_mean, double* blk_m2,
                                 int64_t* n_accept, int64_t* n_divergent);
+
+/* Checkpoint and resume.  pcv_save writes everything a run carries between
+ * transitions to the file `path`:
+ * - the accepted positions, gradients, log pi and log predictive of every chain;
+ * - every online accumulator (Algorithm A2) and the accept/divergence counters;
+ * - the transition count.
+ * The write goes to `path`.tmp first and is renamed into place.
+ * pcv_load restores such a file into a context made by pcv_init with the
+ * same model, data, folds and precision (checked against a fingerprint of
+ * X, y and the folds).  Because every random number is keyed by (seed,
+ * chain, transition), the resumed run continues exactly as the original
+ * would have.  Errors: PCV_ERR_INVALID_ARG for an unwritable or unreadable
+ * path, a file of another run, or a truncated or corrupted file (the ctx is
+ * unchanged then); PCV_ERR_DEVICE.  Both synchronise. */
+pcv_status pcv_save(pcv_ctx ctx, const char* path);
+pcv_status pcv_load(pcv_ctx ctx, const char* path);
 
 /* Philox4x32-10 of this library for n counters (c0, c1, c2, c3 + i) with key
  * (seed): out receives 4*n uint32 words.  Host-side buffers; runs on the

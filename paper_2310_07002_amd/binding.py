@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "PCV_OK", 1: "PCV_ERR_INVALID_ARG", 2: "PCV_ERR_NOMEM", 3: "P
 EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_elpd",
             "pcv_shuffle_benchmark", "pcv_destroy", "pcv_last_error", "pcv_status_str",
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
-            "pcv_get_accumulators", "pcv_philox", "pcv_timing_enable", "pcv_timing_read"]
+            "pcv_get_accumulators", "pcv_save", "pcv_load", "pcv_philox", "pcv_timing_enable",
+            "pcv_timing_read"]
 
 
 class PcvError(RuntimeError):
@@ -51,7 +52,11 @@ class pcv_model(ctypes.Structure):
                 ("init_pos", ctypes.POINTER(ctypes.c_double)),
                 ("n_warmup", ctypes.c_int64), ("batch_size", ctypes.c_int32),
                 ("batches_per_block", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64)]
+                ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64),
+                ("x_format", ctypes.c_int32), ("rhat_mode", ctypes.c_int32)]
+
+X_FP64, X_BF16_HILO = 0, 1
+RHAT_WELFORD, RHAT_SHIFTED_SUMS = 0, 1
 
 
 class pcv_diag(ctypes.Structure):
@@ -79,7 +84,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     P, I32, I64, U64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     dp = ctypes.POINTER(ctypes.c_double)
     sig = {
-        "pcv_init": ([ctypes.POINTER(P), ctypes.POINTER(pcv_model), dp, dp, ctypes.POINTER(pcv_folds)], I32),
+        "pcv_init": ([ctypes.POINTER(P), ctypes.POINTER(pcv_model), P, dp, ctypes.POINTER(pcv_folds)], I32),
         "pcv_set_stream": ([P, P], I32),
         "pcv_step": ([P, I64], I32),
         "pcv_diagnostics": ([P, ctypes.POINTER(pcv_diag)], I32),
@@ -93,6 +98,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_get_state": ([P, dp, dp, dp], I32),
         "pcv_set_state": ([P, dp], I32),
         "pcv_get_accumulators": ([P, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
+        "pcv_save": ([P, ctypes.c_char_p], I32),
+        "pcv_load": ([P, ctypes.c_char_p], I32),
         "pcv_philox": ([U64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, I64,
                         ctypes.POINTER(ctypes.c_uint32)], I32),
         "pcv_timing_enable": ([P, I32], I32),
@@ -137,11 +144,18 @@ class PCV:
                  n_groups: int = 0, sigma: float = 1.0, prior_scale=None, step_size: float,
                  n_leapfrog: int, inv_mass, init_pos, n_warmup: int, batch_size: int,
                  batches_per_block: int, n_blocks: int, seed: int, chain_offset: int = 0,
-                 stream=None):
+                 x_format: int = X_FP64, rhat_mode: int = RHAT_WELFORD, stream=None):
+        """X: [n, p] float64, or with x_format=X_BF16_HILO a [2, n, p] uint16
+        array of bf16 bit patterns (hi plane, lo plane)."""
         self._lib = load_library()
-        X = np.ascontiguousarray(X, dtype=np.float64)
+        if x_format == X_BF16_HILO:
+            X = np.ascontiguousarray(X, dtype=np.uint16)
+            assert X.ndim == 3 and X.shape[0] == 2, "bf16 planes must be [2, n, p]"
+            n, p = X.shape[1:]
+        else:
+            X = np.ascontiguousarray(X, dtype=np.float64)
+            n, p = X.shape
         y = np.ascontiguousarray(y, dtype=np.float64)
-        n, p = X.shape
         self.n, self.p, self.K, self.L = n, p, int(K), int(L)
         self.C = self.K * self.L
         self.d = p + 2 + n_groups if group_of is not None else p
@@ -174,13 +188,15 @@ class PCV:
         m.n_warmup, m.batch_size = n_warmup, batch_size
         m.batches_per_block, m.n_blocks = batches_per_block, n_blocks
         m.seed, m.chain_offset = seed, chain_offset
+        m.x_format, m.rhat_mode = x_format, rhat_mode
         f = pcv_folds()
         f.kind = fold_kind
         f.fold_index = fi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if fi is not None else None
         f.intervals = iv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if iv is not None else None
         f.roles = rl.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)) if rl is not None else None
         self._ctx = ctypes.c_void_p()
-        st = self._lib.pcv_init(ctypes.byref(self._ctx), ctypes.byref(m), _dptr(X), _dptr(y), ctypes.byref(f))
+        st = self._lib.pcv_init(ctypes.byref(self._ctx), ctypes.byref(m), X.ctypes.data_as(ctypes.c_void_p),
+                                _dptr(y), ctypes.byref(f))
         if st != PCV_OK:
             self._ctx = None
             raise PcvError(st, "pcv_init failed (details on stderr)")
@@ -188,9 +204,13 @@ class PCV:
             self.set_stream(stream)
 
     @classmethod
-    def from_workload(cls, w, precision: Optional[int] = None, stream=None) -> "PCV":
+    def from_workload(cls, w, precision: Optional[int] = None, stream=None, x_planes: bool = False,
+                      rhat_mode: int = RHAT_WELFORD) -> "PCV":
+        """x_planes: pass the design as its stored bf16 hi/lo planes (w.x_hi, w.x_lo)."""
+        X, xf = (np.stack([w.x_hi, w.x_lo]), X_BF16_HILO) if x_planes else (w.X, X_FP64)
         return cls(family=w.family, precision=w.precision if precision is None else precision,
-                   X=w.X, y=w.y, K=w.K, L=w.L, fold_kind=w.fold_kind, fold_index=w.fold_index,
+                   X=X, x_format=xf, rhat_mode=rhat_mode, y=w.y, K=w.K, L=w.L, fold_kind=w.fold_kind,
+                   fold_index=w.fold_index,
                    intervals=w.intervals, roles=w.roles, group_of=w.group_of, n_groups=w.n_groups,
                    sigma=w.sigma, prior_scale=w.prior_scale, step_size=w.step_size,
                    n_leapfrog=w.n_leapfrog, inv_mass=w.inv_mass, init_pos=w.init_pos,
@@ -295,6 +315,14 @@ class PCV:
         out["blk_mean"] = out["blk_mean"].reshape(n_blocks, C).T.copy()
         out["blk_m2"] = out["blk_m2"].reshape(n_blocks, C).T.copy()
         return out
+
+    def save(self, path: str):
+        """Checkpoint the run (state, accumulators, transition count) to `path`."""
+        self._check(self._lib.pcv_save(self._ctx, os.fsencode(path)), "pcv_save")
+
+    def load(self, path: str):
+        """Resume from a checkpoint of the same model, data, folds and precision."""
+        self._check(self._lib.pcv_load(self._ctx, os.fsencode(path)), "pcv_load")
 
     def timing_enable(self, on: bool = True):
         self._check(self._lib.pcv_timing_enable(self._ctx, 1 if on else 0), "pcv_timing_enable")

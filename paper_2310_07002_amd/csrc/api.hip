@@ -91,12 +91,33 @@ struct pcv_ctx_s {
   int64_t n_launch = 0;
   std::string err;
   bool dead = false;
+  uint64_t fingerprint = 0;   // of X, y, folds and groups (checkpoints)
 };
 
 namespace {
 
 const char* kGradKernelName[3] = {"k_valu (fused transition)", "k_mfma (bf16 split MFMA value+gradient)",
                                   "rocblas_dgemm + k_unfused_resid (fp64 unfused)"};
+
+// Fingerprint of input arrays (FNV-1a over 8-byte words plus a shift to
+// spread high bits; not cryptographic): a checkpoint only resumes a run on
+// the same data.
+uint64_t fp_mix(uint64_t h, const void* data, size_t bytes) {
+  const unsigned char* b = static_cast<const unsigned char*>(data);
+  size_t i = 0;
+  for (; i + 8 <= bytes; i += 8) {
+    uint64_t w;
+    std::memcpy(&w, b + i, 8);
+    h ^= w;
+    h *= 0x100000001b3ULL;
+    h ^= h >> 29;
+  }
+  for (; i < bytes; ++i) {
+    h ^= b[i];
+    h *= 0x100000001b3ULL;
+  }
+  return h;
+}
 
 pcv_status fail(pcv_ctx ctx, pcv_status s, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -318,6 +339,11 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   if (md->L < 2 || md->L > 64) return fail(ctx, PCV_ERR_INVALID_ARG, "L must be in [2, 64]");
   if (md->family < 0 || md->family > 3) return fail(ctx, PCV_ERR_INVALID_ARG, "unknown family");
   if (md->precision < 0 || md->precision > 4) return fail(ctx, PCV_ERR_INVALID_ARG, "unknown precision");
+  if (md->x_format != PCV_X_FP64 && md->x_format != PCV_X_BF16_HILO)
+    return fail(ctx, PCV_ERR_INVALID_ARG, "unknown x_format");
+  if (md->rhat_mode != PCV_RHAT_WELFORD && md->rhat_mode != PCV_RHAT_SHIFTED_SUMS)
+    return fail(ctx, PCV_ERR_INVALID_ARG, "unknown rhat_mode");
+  if (md->rhat_mode == PCV_RHAT_SHIFTED_SUMS) return fail(ctx, PCV_ERR_UNSUPPORTED, "rhat_mode not built");
   if (!(md->step_size > 0) || !std::isfinite(md->step_size)) return fail(ctx, PCV_ERR_INVALID_ARG, "step_size must be > 0");
   if (md->n_leapfrog < 1) return fail(ctx, PCV_ERR_INVALID_ARG, "n_leapfrog must be >= 1");
   if (md->batch_size < 1 || md->batches_per_block < 1 || md->n_blocks < 1 || md->n_blocks > MAX_BLOCKS)
@@ -410,6 +436,16 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
 
   // ---- path selection ------------------------------------------------------
   ctx->prec = md->precision;
+  {
+    uint64_t h = 0xcbf29ce484222325ULL;
+    h = fp_mix(h, X, sizeof(double) * static_cast<size_t>(n * p));
+    h = fp_mix(h, y, sizeof(double) * static_cast<size_t>(n));
+    if (fm->kind == PCV_FOLDS_INDEX) h = fp_mix(h, fm->fold_index, sizeof(int32_t) * static_cast<size_t>(n));
+    if (fm->kind == PCV_FOLDS_INTERVALS) h = fp_mix(h, fm->intervals, sizeof(int64_t) * 4 * static_cast<size_t>(K));
+    if (fm->kind == PCV_FOLDS_DENSE) h = fp_mix(h, fm->roles, static_cast<size_t>(K) * static_cast<size_t>(n));
+    if (hier) h = fp_mix(h, md->group_of, sizeof(int32_t) * static_cast<size_t>(n));
+    ctx->fingerprint = h;
+  }
   if (md->precision == PCV_PREC_FP64 || md->precision == PCV_PREC_FP32) {
     ctx->path = PATH_VALU;
     ctx->fp64 = md->precision == PCV_PREC_FP64;
@@ -645,13 +681,41 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   return PCV_OK;
 }
 
-pcv_status pcv_init(pcv_ctx* out, const pcv_model* model, const double* X, const double* y,
+pcv_status pcv_init(pcv_ctx* out, const pcv_model* model, const void* X, const double* y,
                     const pcv_folds* fold_masks) {
   if (!out) return PCV_ERR_INVALID_ARG;
   *out = nullptr;
   pcv_ctx ctx = new (std::nothrow) pcv_ctx_s();
   if (!ctx) return PCV_ERR_NOMEM;
-  pcv_status s = init_impl(ctx, model, X, y, fold_masks);
+  // a design given as two bf16 planes is summed (exactly) into fp64 here
+  std::vector<double> x_sum;
+  const double* X64 = static_cast<const double*>(X);
+  pcv_status s = PCV_OK;
+  if (model && X && model->x_format == PCV_X_BF16_HILO) {
+    if (model->n <= 0 || model->p <= 0 || model->n > (int64_t{1} << 40) / model->p) {
+      s = fail(ctx, PCV_ERR_INVALID_ARG, "n and p must be positive");
+    } else {
+      const size_t np = static_cast<size_t>(model->n * model->p);
+      const uint16_t* hi = static_cast<const uint16_t*>(X);
+      const uint16_t* lo = hi + np;
+      auto bf = [](uint16_t b) {
+        const uint32_t u = static_cast<uint32_t>(b) << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return static_cast<double>(f);
+      };
+      try {
+        x_sum.resize(np);
+      } catch (...) {
+        s = fail(ctx, PCV_ERR_NOMEM, "host memory for X");
+      }
+      if (s == PCV_OK) {
+        for (size_t i = 0; i < np; ++i) x_sum[i] = bf(hi[i]) + bf(lo[i]);
+        X64 = x_sum.data();
+      }
+    }
+  }
+  if (s == PCV_OK) s = init_impl(ctx, model, X64, y, fold_masks);
   if (s != PCV_OK) {
     // keep the message available through a static copy: the context dies here
     static thread_local std::string last;
@@ -878,6 +942,141 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
   if (blk_m2) CK(hipMemcpy(blk_m2, m.bm2, sizeof(double) * DC, hipMemcpyDeviceToHost));
   if (n_accept) CK(hipMemcpy(n_accept, m.nacc, sizeof(int64_t) * C, hipMemcpyDeviceToHost));
   if (n_divergent) CK(hipMemcpy(n_divergent, m.ndiv, sizeof(int64_t) * C, hipMemcpyDeviceToHost));
+  return PCV_OK;
+}
+
+// ---- checkpoints ---------------------------------------------------------
+
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t family, precision, fold_kind;
+  int64_t n, p, d, C;
+  int32_t K, L, D, b, Gb, S;
+  uint64_t seed;
+  int64_t chain_offset, n_warmup;
+  double eps;
+  uint64_t fingerprint;
+  int64_t t;
+  uint64_t payload_bytes;
+  uint64_t payload_hash;
+};
+static_assert(sizeof(CkptHeader) == 144, "checkpoint header has no padding");
+constexpr char kCkptMagic[8] = {'P', 'C', 'V', 'C', 'K', 'P', 'T', '1'};
+
+CkptHeader ckpt_header_of(pcv_ctx ctx) {
+  const DevModel& m = ctx->m;
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.family = m.family;
+  h.precision = ctx->prec;
+  h.fold_kind = m.fold_kind;
+  h.n = m.n;
+  h.p = m.p;
+  h.d = m.d;
+  h.C = m.C;
+  h.K = m.K;
+  h.L = m.L;
+  h.D = m.D;
+  h.b = m.b;
+  h.Gb = m.Gb;
+  h.S = m.S;
+  h.seed = (static_cast<uint64_t>(m.key1) << 32) | m.key0;
+  h.chain_offset = m.chain_offset;
+  h.n_warmup = m.n_warmup;
+  h.eps = m.eps;
+  h.fingerprint = ctx->fingerprint;
+  return h;
+}
+
+// The device arrays a checkpoint holds, in file order: the accepted state and
+// every online accumulator.
+struct CkptArray {
+  void* dev;
+  size_t bytes;
+};
+std::vector<CkptArray> ckpt_arrays(pcv_ctx ctx) {
+  const DevModel& m = ctx->m;
+  const size_t C = m.C, dC = static_cast<size_t>(m.d) * m.C, DC = static_cast<size_t>(m.D) * m.C;
+  return {{m.q0, 8 * dC},  {m.g0, 8 * dC}, {m.logp0, 8 * C}, {m.s0, 8 * C},     {m.Z, 8 * C},
+          {m.U, 8 * C},    {m.U2, 8 * C},  {m.V, 8 * C},     {m.V2, 8 * C},     {m.bmean, 8 * DC},
+          {m.bm2, 8 * DC}, {m.nacc, 8 * C}, {m.ndiv, 8 * C}};
+}
+
+}  // namespace
+
+pcv_status pcv_save(pcv_ctx ctx, const char* path) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!path || !*path) return fail(ctx, PCV_ERR_INVALID_ARG, "null path");
+  CK(hipStreamSynchronize(ctx->st));
+  const std::vector<CkptArray> arrs = ckpt_arrays(ctx);
+  size_t total = 0;
+  for (const CkptArray& a : arrs) total += a.bytes;
+  std::vector<unsigned char> payload(total);
+  size_t off = 0;
+  for (const CkptArray& a : arrs) {
+    CK(hipMemcpy(payload.data() + off, a.dev, a.bytes, hipMemcpyDeviceToHost));
+    off += a.bytes;
+  }
+  CkptHeader h = ckpt_header_of(ctx);
+  h.t = ctx->t;
+  h.payload_bytes = total;
+  h.payload_hash = fp_mix(0xcbf29ce484222325ULL, payload.data(), total);
+  // write to a temporary name, then rename: a crash never leaves a torn file
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(ctx, PCV_ERR_INVALID_ARG, "cannot open " + tmp + " for writing");
+  const bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(payload.data(), 1, total, f) == total;
+  const bool closed = std::fclose(f) == 0;
+  if (!ok || !closed) {
+    std::remove(tmp.c_str());
+    return fail(ctx, PCV_ERR_INVALID_ARG, "write to " + tmp + " failed");
+  }
+  if (std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(ctx, PCV_ERR_INVALID_ARG, std::string("cannot rename checkpoint to ") + path);
+  }
+  return PCV_OK;
+}
+
+pcv_status pcv_load(pcv_ctx ctx, const char* path) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!path || !*path) return fail(ctx, PCV_ERR_INVALID_ARG, "null path");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(ctx, PCV_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  CkptHeader h{};
+  const bool got = std::fread(&h, sizeof(h), 1, f) == 1;
+  const std::vector<CkptArray> arrs = ckpt_arrays(ctx);
+  size_t total = 0;
+  for (const CkptArray& a : arrs) total += a.bytes;
+  std::vector<unsigned char> payload;
+  bool body = false;
+  if (got && std::memcmp(h.magic, kCkptMagic, 8) == 0 && h.payload_bytes == total) {
+    payload.resize(total);
+    body = std::fread(payload.data(), 1, total, f) == total && std::fgetc(f) == EOF;
+  }
+  std::fclose(f);
+  if (!got || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+    return fail(ctx, PCV_ERR_INVALID_ARG, "not a checkpoint of this library");
+  CkptHeader want = ckpt_header_of(ctx);
+  want.t = h.t;
+  want.payload_bytes = h.payload_bytes;
+  want.payload_hash = h.payload_hash;
+  if (std::memcmp(&want, &h, sizeof(h)) != 0)
+    return fail(ctx, PCV_ERR_INVALID_ARG, "checkpoint is of another model, data, fold set or precision");
+  if (!body || fp_mix(0xcbf29ce484222325ULL, payload.data(), total) != h.payload_hash)
+    return fail(ctx, PCV_ERR_INVALID_ARG, "checkpoint is truncated or corrupted");
+  if (h.t < 0 || h.t > 0xFFFFFFFFLL) return fail(ctx, PCV_ERR_INVALID_ARG, "checkpoint iteration out of range");
+  CK(hipStreamSynchronize(ctx->st));
+  size_t off = 0;
+  for (const CkptArray& a : arrs) {
+    CK(hipMemcpy(a.dev, payload.data() + off, a.bytes, hipMemcpyHostToDevice));
+    off += a.bytes;
+  }
+  ctx->t = h.t;
   return PCV_OK;
 }
 

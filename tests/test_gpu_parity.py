@@ -309,6 +309,66 @@ def test_state_roundtrip_and_divergence_counting(dev):
     np.testing.assert_allclose(lp1, lp0, rtol=1e-15)
 
 
+def test_design_as_bf16_planes_matches_fp64_design(dev, tmp_path):
+    """X handed over as its stored bf16 hi/lo planes is the same design as its
+    fp64 sum: identical results, and checkpoints are interchangeable."""
+    w = W.fold_subset(W.make("c4"), 0, 24)
+    a = binding.PCV.from_workload(w, precision=W.PREC_BF16X3)
+    b = binding.PCV.from_workload(w, precision=W.PREC_BF16X3, x_planes=True)
+    theta = torch.tensor(_theta_near_init(w, seed=2), device=dev)
+    for x, y in zip(a.logdensity_grad(theta), b.logdensity_grad(theta)):
+        torch.testing.assert_close(x, y, rtol=0, atol=0)
+    a.step(3)
+    a.save(str(tmp_path / "a.ckpt"))
+    b.load(str(tmp_path / "a.ckpt"))
+    b.step(2)
+    a.step(2)
+    for x, y in zip(a.get_state(), b.get_state()):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("name,prec,folds_", [("c1", "fp64", (0, 12)), ("c4", "bf16x3", (0, 40))])
+def test_checkpoint_resume_is_exact(dev, tmp_path, name, prec, folds_):
+    """Run A: 30 transitions, save, 25 more.  Run B: a fresh context loads the
+    checkpoint and runs 25.  Everything must agree bit for bit (random
+    numbers are keyed by chain and transition).  Checkpoints of another run
+    and damaged files are refused and leave the context usable."""
+    w = dataclasses.replace(W.fold_subset(W.make(name), *folds_), n_warmup=12, batch_size=4)
+    path = str(tmp_path / "run.ckpt")
+    _say(f"[checkpoint] {name} {prec} C={w.C}")
+    a = binding.PCV.from_workload(w, precision=PREC[prec])
+    a.step(30)
+    a.save(path)
+    a.step(25)
+    b = binding.PCV.from_workload(w, precision=PREC[prec])
+    b.load(path)
+    b.step(25)
+    for x, y in zip(a.get_state(), b.get_state()):
+        np.testing.assert_array_equal(x, y)
+    acc_a, acc_b = a.get_accumulators(w.n_blocks), b.get_accumulators(w.n_blocks)
+    for k in acc_a:
+        np.testing.assert_array_equal(acc_a[k], acc_b[k])
+    da, db = a.diagnostics(), b.diagnostics()
+    assert da["n_iter"] == db["n_iter"] == 55
+    assert da["elpd"] == db["elpd"] and da["rhat_max"] == db["rhat_max"]
+
+    other = binding.PCV.from_workload(dataclasses.replace(w, seed=w.seed + 1), precision=PREC[prec])
+    with pytest.raises(binding.PcvError, match="another"):
+        other.load(path)
+    raw = bytearray(open(path, "rb").read())
+    raw[len(raw) // 2] ^= 0x40
+    bad = str(tmp_path / "flipped.ckpt")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(binding.PcvError, match="corrupted"):
+        b.load(bad)
+    short = str(tmp_path / "short.ckpt")
+    open(short, "wb").write(bytes(raw[: len(raw) - 8]))
+    with pytest.raises(binding.PcvError, match="corrupted"):
+        b.load(short)
+    b.step(1)                                   # still usable after refused loads
+    assert b.diagnostics()["n_iter"] == 56
+
+
 @pytest.mark.parametrize("name,prec,tol_g", [("c5", "bf16x3", 5e-5), ("c4", "bf16x3", 5e-5), ("c5", "bf16x5", 1e-5)])
 def test_full_size_sampled_parity(dev, name, prec, tol_g):
     """The full configuration in the launch shape the benchmark times (all
