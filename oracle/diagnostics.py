@@ -59,6 +59,20 @@ def merge_blocks(blk_n, blk_mean, blk_m2):
     return n, mean, m2
 
 
+def chain_moments(acc):
+    """Per-chain (n, mean, M2) of s over all blocks, from either block mode.
+    Shifted sums give the mean relative to C_k, which Rhat does not see."""
+    if getattr(acc, "mode", 0) == 1:
+        n = acc.blk_n.sum(axis=-1).astype(np.float64)
+        y = acc.blk_mean.sum(axis=-1)
+        y2 = acc.blk_m2.sum(axis=-1)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            mean = np.where(n > 0, y / np.maximum(n, 1), 0.0)
+            m2 = y2 - np.where(n > 0, y * y / np.maximum(n, 1), 0.0)
+        return n, mean, m2
+    return merge_blocks(acc.blk_n, acc.blk_mean, acc.blk_m2)
+
+
 def rhat_from_moments(N, chain_mean, chain_m2):
     """Rhat of one fold from per-chain means [L] and M2 [L] (N draws each)."""
     L = chain_mean.shape[-1]
@@ -90,7 +104,7 @@ def from_accumulators(acc, K: int, L: int, b: int) -> dict:
     out["elpd_fold"] = elpd_k
     out["elpd"] = float(np.sum(elpd_k))
     # Rhat
-    n, mean, m2 = merge_blocks(acc.blk_n, acc.blk_mean, acc.blk_m2)
+    n, mean, m2 = chain_moments(acc)
     if N >= 2:
         rk = rhat_from_moments(float(N), mean.reshape(K, L), m2.reshape(K, L))
     else:
@@ -179,9 +193,21 @@ def shuffle_benchmark(acc, K: int, L: int, D: int, R: int, seed: int, fold_offse
             n = np.zeros(L)
             mean = np.zeros(L)
             m2 = np.zeros(L)
-            for dd in range(D):
-                src = idx[:, dd]
-                n, mean, m2 = _chan_merge(n, mean, m2, bn[k, src, dd].astype(np.float64),
-                                          bm[k, src, dd], b2[k, src, dd])
+            if getattr(acc, "mode", 0) == 1:
+                # shifted sums: a rebuilt chain's Y and Y2 are sums of its blocks'
+                y = np.zeros(L)
+                y2 = np.zeros(L)
+                for dd in range(D):
+                    src = idx[:, dd]
+                    n = n + bn[k, src, dd]
+                    y = y + bm[k, src, dd]
+                    y2 = y2 + b2[k, src, dd]
+                mean = y / n
+                m2 = y2 - y * y / n
+            else:
+                for dd in range(D):
+                    src = idx[:, dd]
+                    n, mean, m2 = _chan_merge(n, mean, m2, bn[k, src, dd].astype(np.float64),
+                                              bm[k, src, dd], b2[k, src, dd])
             out[k, r] = rhat_from_moments(N, mean, m2)
     return out, out.max(axis=0)

@@ -15,10 +15,15 @@ current draw:
                    V2 <- logaddexp(V2, 2Z - 2 log b)
                    Z  <- -inf
 
-Reading: the paper accumulates shifted sums of s and s^2 per block around a
-warm-up centring constant (Appendix A.1); Welford's running mean and M2 per
-block give the same within/between-chain variances without the centring
-constant and without cancellation.  Draws past D*G*b go to the last block.  A
+Block statistics for Rhat come in two modes (rhat_mode of the workload):
+  0  Welford: running (count, mean, M2) of s per block, Chan-merged later;
+  1  shifted sums, as Algorithm A2 writes them: during warm-up every draw of
+     every chain of fold k adds to the fold's centring constant
+     C_k = mean of the fold's L*N_wu warm-up log predictive draws; afterwards
+     each block keeps Y = sum (s - C_k) and Y2 = sum (s - C_k)^2.
+Both give the same within/between-chain variances (the shift cancels); the
+Welford form avoids the cancellation in Y2 - Y^2/N.  Draws past D*G*b go to
+the last block.  A
 partial batch is part of U (through Z), U2 and the block statistics, and is
 left out of V, V2.  Accept and divergence counts cover post-warm-up
 transitions.
@@ -37,6 +42,9 @@ import numpy as np
 from . import folds, hmc
 
 
+RHAT_WELFORD, RHAT_SHIFTED_SUMS = 0, 1
+
+
 @dataclasses.dataclass
 class Accumulators:
     Z: np.ndarray
@@ -45,20 +53,41 @@ class Accumulators:
     V: np.ndarray
     V2: np.ndarray
     blk_n: np.ndarray      # [C, D] int64
-    blk_mean: np.ndarray   # [C, D]
-    blk_m2: np.ndarray     # [C, D]
+    blk_mean: np.ndarray   # [C, D] Welford mean of s         | shifted: Y  = sum (s - C_k)
+    blk_m2: np.ndarray     # [C, D] Welford M2 of s           | shifted: Y2 = sum (s - C_k)^2
     n_draws: int = 0
     n_accept: Optional[np.ndarray] = None
     n_divergent: Optional[np.ndarray] = None
+    mode: int = RHAT_WELFORD
+    wsum: Optional[np.ndarray] = None      # [C] sum of warm-up draws of s (shifted mode)
+    n_wu: int = 0                          # warm-up draws summed so far
+    center: Optional[np.ndarray] = None    # [C] C_k of each chain's fold (shifted mode)
 
     @staticmethod
-    def empty(C: int, D: int) -> "Accumulators":
+    def empty(C: int, D: int, mode: int = RHAT_WELFORD) -> "Accumulators":
         ninf = lambda: np.full(C, -np.inf)
         return Accumulators(Z=ninf(), U=ninf(), U2=ninf(), V=ninf(), V2=ninf(),
                             blk_n=np.zeros((C, D), dtype=np.int64),
                             blk_mean=np.zeros((C, D)), blk_m2=np.zeros((C, D)),
                             n_draws=0, n_accept=np.zeros(C, dtype=np.int64),
-                            n_divergent=np.zeros(C, dtype=np.int64))
+                            n_divergent=np.zeros(C, dtype=np.int64), mode=mode,
+                            wsum=np.zeros(C), n_wu=0, center=np.zeros(C))
+
+
+def warmup_draw(acc: Accumulators, s: np.ndarray) -> None:
+    """Shifted mode: a warm-up draw adds to its fold's centring constant."""
+    if acc.mode == RHAT_SHIFTED_SUMS:
+        acc.wsum += s
+        acc.n_wu += 1
+
+
+def fix_center(acc: Accumulators, L: int) -> None:
+    """Shifted mode, end of warm-up: C_k = mean of the fold's L * N_wu warm-up
+    draws (0 when there was no warm-up), copied to each of its chains."""
+    if acc.mode == RHAT_SHIFTED_SUMS:
+        K = acc.wsum.size // L
+        ck = acc.wsum.reshape(K, L).sum(axis=1) / (L * acc.n_wu) if acc.n_wu > 0 else np.zeros(K)
+        acc.center = np.repeat(ck, L)
 
 
 def accumulate(acc: Accumulators, s: np.ndarray, i: int, b: int, G: int, D: int) -> None:
@@ -67,10 +96,15 @@ def accumulate(acc: Accumulators, s: np.ndarray, i: int, b: int, G: int, D: int)
     acc.U2 = np.logaddexp(acc.U2, 2.0 * s)
     blk = min(i // (G * b), D - 1)
     acc.blk_n[:, blk] += 1
-    n = acc.blk_n[:, blk].astype(np.float64)
-    delta = s - acc.blk_mean[:, blk]
-    acc.blk_mean[:, blk] += delta / n
-    acc.blk_m2[:, blk] += delta * (s - acc.blk_mean[:, blk])
+    if acc.mode == RHAT_SHIFTED_SUMS:
+        dv = s - acc.center
+        acc.blk_mean[:, blk] += dv
+        acc.blk_m2[:, blk] += dv * dv
+    else:
+        n = acc.blk_n[:, blk].astype(np.float64)
+        delta = s - acc.blk_mean[:, blk]
+        acc.blk_mean[:, blk] += delta / n
+        acc.blk_m2[:, blk] += delta * (s - acc.blk_mean[:, blk])
     if (i + 1) % b == 0:
         acc.U = np.logaddexp(acc.U, acc.Z)
         acc.V = np.logaddexp(acc.V, acc.Z - math.log(b))
@@ -92,7 +126,10 @@ def start(w) -> Run:
     roles = folds.roles_of(w)
     foc = np.arange(w.C) // w.L
     st = hmc.initial_state(w, roles, foc)
-    return Run(state=st, acc=Accumulators.empty(w.C, w.n_blocks), t=0)
+    acc = Accumulators.empty(w.C, w.n_blocks, getattr(w, "rhat_mode", RHAT_WELFORD))
+    if w.n_warmup == 0:
+        fix_center(acc, w.L)
+    return Run(state=st, acc=acc, t=0)
 
 
 def advance(w, run: Run, n_iter: int, store_draws: bool = False,
@@ -109,7 +146,11 @@ def advance(w, run: Run, n_iter: int, store_draws: bool = False,
         run.state, accepted, divergent = hmc.transition(w, run.state, t, roles, foc, chain_ids)
         if store_accepts:
             accs.append(accepted.copy())
-        if t >= w.n_warmup:
+        if t < w.n_warmup:
+            warmup_draw(run.acc, run.state.s)
+            if t + 1 == w.n_warmup:
+                fix_center(run.acc, w.L)
+        else:
             accumulate(run.acc, run.state.s, t - w.n_warmup, b, G, D)
             run.acc.n_accept += accepted
             run.acc.n_divergent += divergent

@@ -205,9 +205,12 @@ class PCV:
 
     @classmethod
     def from_workload(cls, w, precision: Optional[int] = None, stream=None, x_planes: bool = False,
-                      rhat_mode: int = RHAT_WELFORD) -> "PCV":
-        """x_planes: pass the design as its stored bf16 hi/lo planes (w.x_hi, w.x_lo)."""
+                      rhat_mode: Optional[int] = None) -> "PCV":
+        """x_planes: pass the design as its stored bf16 hi/lo planes (w.x_hi, w.x_lo).
+        rhat_mode: default the workload's."""
         X, xf = (np.stack([w.x_hi, w.x_lo]), X_BF16_HILO) if x_planes else (w.X, X_FP64)
+        if rhat_mode is None:
+            rhat_mode = getattr(w, "rhat_mode", RHAT_WELFORD)
         return cls(family=w.family, precision=w.precision if precision is None else precision,
                    X=X, x_format=xf, rhat_mode=rhat_mode, y=w.y, K=w.K, L=w.L, fold_kind=w.fold_kind,
                    fold_index=w.fold_index,

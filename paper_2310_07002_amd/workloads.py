@@ -87,6 +87,7 @@ class Workload:
     n_blocks: int = 5
     seed: int = 0                              # Philox key of the sampler
     chain_offset: int = 0                      # global id of chain 0
+    rhat_mode: int = 0                         # 0 Welford blocks, 1 shifted sums (Algorithm A2)
     truth: Optional[np.ndarray] = None         # [d]
     x_hi: Optional[np.ndarray] = None          # [n, p] uint16 bf16 bits
     x_lo: Optional[np.ndarray] = None          # [n, p] uint16 bf16 bits

@@ -115,3 +115,36 @@ def test_fold_subset_replays_the_same_chains():
     sub = sampler.run_all(W.fold_subset(w, 10, 14), n_iter=8, store_draws=True)
     np.testing.assert_array_equal(sub.state.q, full.state.q[10 * w.L:14 * w.L])
     np.testing.assert_array_equal(sub.draws, full.draws[10 * w.L:14 * w.L])
+
+
+def test_shifted_sums_mode_matches_welford_and_two_pass():
+    """Algorithm A2's shifted sums: C_k is the mean of the fold's L*N_wu
+    warm-up draws, each block keeps sum (s - C_k) and sum (s - C_k)^2, and
+    Rhat and its block-shuffle benchmark equal the Welford and two-pass
+    values on the same draws (the shift cancels)."""
+    w = W.fold_subset(dataclasses.replace(W.make_c1(), n_warmup=40, rhat_mode=1), 0, 10)
+    b, G, D = w.batch_size, w.batches_per_block, w.n_blocks
+    run = sampler.start(w)
+    wu = []
+    for _ in range(w.n_warmup):
+        sampler.advance(w, run, 1)
+        wu.append(run.state.s.copy())
+    wu = np.stack(wu, axis=1).reshape(w.K, w.L * w.n_warmup)
+    np.testing.assert_allclose(run.acc.center, np.repeat(wu.mean(axis=1), w.L), rtol=1e-13)
+    N = 237                                        # blocks of G*b = 200 draws: one full, one partial
+    sampler.advance(w, run, N, store_draws=True)
+    y = run.draws - run.acc.center[:, None]
+    for dd in range(D):
+        seg = y[:, dd * G * b:(dd + 1) * G * b] if dd < D - 1 else y[:, dd * G * b:]
+        np.testing.assert_allclose(run.acc.blk_mean[:, dd], seg.sum(axis=1), rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(run.acc.blk_m2[:, dd], (seg * seg).sum(axis=1), rtol=1e-11, atol=1e-11)
+    wf = sampler.run_all(dataclasses.replace(w, rhat_mode=0), n_iter=w.n_warmup + N)
+    np.testing.assert_array_equal(wf.state.s, run.state.s)
+    on_s = diagnostics.from_accumulators(run.acc, w.K, w.L, b)
+    on_w = diagnostics.from_accumulators(wf.acc, w.K, w.L, b)
+    tp = diagnostics.two_pass(run.draws, w.K, w.L, b)
+    np.testing.assert_allclose(on_s["rhat_fold"], on_w["rhat_fold"], rtol=1e-10)
+    np.testing.assert_allclose(on_s["rhat_fold"], tp["rhat_fold"], rtol=1e-10)
+    _, rep_s = diagnostics.shuffle_benchmark(run.acc, w.K, w.L, D, 20, seed=3)
+    _, rep_w = diagnostics.shuffle_benchmark(wf.acc, w.K, w.L, D, 20, seed=3)
+    np.testing.assert_allclose(rep_s, rep_w, rtol=1e-9)
