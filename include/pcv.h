@@ -212,7 +212,9 @@ pcv_status pcv_set_state(pcv_ctx ctx, const double* theta);
 
 /* Raw online accumulators (Algorithm A2) to host buffers, any may be NULL:
  * Z, U, U2, V, V2: C each (log scale); blk_mean, blk_m2: D*C each
- * (block-major: [dd*C + c]); n_accept, n_divergent: C each. */
+ * (block-major: [dd*C + c]) holding the Welford mean and M2 of s per block,
+ * or with rhat_mode PCV_RHAT_SHIFTED_SUMS the sums of s - C_k and
+ * (s - C_k)^2; n_accept, n_divergent: C each. */
 pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, double* V,
                                 double* V2, double* blk_mean, double* blk_m2,
                                 int64_t* n_accept, int64_t* n_divergent);

@@ -28,6 +28,7 @@ hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st);
 hipError_t launch_reduce_f32(const DevModel& m, const float* G, int ns, int mode, hipStream_t st);
 hipError_t launch_reduce_f64(const DevModel& m, const double* G, int ns, int mode, hipStream_t st);
 hipError_t launch_value_finish(const DevModel& m, const double* V, int ns, hipStream_t st);
+hipError_t launch_center(const DevModel& m, hipStream_t st);
 hipError_t launch_accept(const DevModel& m, const double* V, int ns, int64_t t, hipStream_t st);
 hipError_t launch_logpred(const DevModel& m, hipStream_t st);
 hipError_t launch_unfused_resid(const DevModel& m, double* eta, int64_t c0, int64_t cc, double* V, int want_value,
@@ -343,7 +344,6 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown x_format");
   if (md->rhat_mode != PCV_RHAT_WELFORD && md->rhat_mode != PCV_RHAT_SHIFTED_SUMS)
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown rhat_mode");
-  if (md->rhat_mode == PCV_RHAT_SHIFTED_SUMS) return fail(ctx, PCV_ERR_UNSUPPORTED, "rhat_mode not built");
   if (!(md->step_size > 0) || !std::isfinite(md->step_size)) return fail(ctx, PCV_ERR_INVALID_ARG, "step_size must be > 0");
   if (md->n_leapfrog < 1) return fail(ctx, PCV_ERR_INVALID_ARG, "n_leapfrog must be >= 1");
   if (md->batch_size < 1 || md->batches_per_block < 1 || md->n_blocks < 1 || md->n_blocks > MAX_BLOCKS)
@@ -479,6 +479,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   m.eps = md->step_size;
   m.S = md->n_leapfrog;
   m.n_warmup = md->n_warmup;
+  m.rhat_mode = md->rhat_mode;
   m.b = md->batch_size;
   m.Gb = md->batches_per_block;
   m.D = md->n_blocks;
@@ -562,6 +563,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   TRY(dalloc(ctx, &m.bm2, static_cast<size_t>(m.D) * C));
   TRY(dalloc(ctx, &m.nacc, C));
   TRY(dalloc(ctx, &m.ndiv, C));
+  TRY(dalloc(ctx, &m.wsum, C));
+  TRY(dalloc(ctx, &m.center, static_cast<size_t>(K)));
   TRY(dalloc(ctx, &m.t_dev, 1));
   TRY(dalloc(ctx, &ctx->fold_buf, 6 * static_cast<size_t>(K)));
   TRY(dalloc(ctx, &ctx->dscal, 8));
@@ -675,6 +678,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   CK(launch_fill(m.V2, -INFINITY, C, ctx->st));
   CK(launch_fill(m.bmean, 0.0, static_cast<int64_t>(m.D) * C, ctx->st));
   CK(launch_fill(m.bm2, 0.0, static_cast<int64_t>(m.D) * C, ctx->st));
+  CK(launch_fill(m.wsum, 0.0, C, ctx->st));
+  CK(launch_fill(m.center, 0.0, K, ctx->st));
   CK(hipMemsetAsync(m.nacc, 0, sizeof(int64_t) * C, ctx->st));
   CK(hipMemsetAsync(m.ndiv, 0, sizeof(int64_t) * C, ctx->st));
   CK(hipStreamSynchronize(ctx->st));
@@ -735,10 +740,24 @@ pcv_status pcv_set_stream(pcv_ctx ctx, void* hip_stream) {
   return PCV_OK;
 }
 
+static pcv_status step_run(pcv_ctx ctx, int64_t n_iter);
+
 pcv_status pcv_step(pcv_ctx ctx, int64_t n_iter) {
   if (!usable(ctx)) return PCV_ERR_STATE;
   if (n_iter < 0) return fail(ctx, PCV_ERR_INVALID_ARG, "n_iter must be >= 0");
   if (ctx->t + n_iter > 0xFFFFFFFFLL) return fail(ctx, PCV_ERR_INVALID_ARG, "iteration counter exceeds 32 bits");
+  const int64_t nw = ctx->m.n_warmup;
+  if (ctx->m.rhat_mode == PCV_RHAT_SHIFTED_SUMS && nw > 0 && ctx->t < nw && ctx->t + n_iter >= nw) {
+    // shifted sums: the fold centres C_k are fixed when the warm-up ends
+    const int64_t first = nw - ctx->t;
+    TRY(step_run(ctx, first));
+    CK(launch_center(ctx->m, ctx->st));
+    return step_run(ctx, n_iter - first);
+  }
+  return step_run(ctx, n_iter);
+}
+
+static pcv_status step_run(pcv_ctx ctx, int64_t n_iter) {
   if (ctx->path == PATH_VALU) {
     // one launch runs many whole transitions; chunk to keep launches bounded
     const int64_t chunk = 256;
@@ -954,7 +973,7 @@ struct CkptHeader {
   uint32_t version;
   int32_t family, precision, fold_kind;
   int64_t n, p, d, C;
-  int32_t K, L, D, b, Gb, S;
+  int32_t K, L, D, b, Gb, S, rhat_mode, reserved;
   uint64_t seed;
   int64_t chain_offset, n_warmup;
   double eps;
@@ -963,7 +982,7 @@ struct CkptHeader {
   uint64_t payload_bytes;
   uint64_t payload_hash;
 };
-static_assert(sizeof(CkptHeader) == 144, "checkpoint header has no padding");
+static_assert(sizeof(CkptHeader) == 152, "checkpoint header has no padding");
 constexpr char kCkptMagic[8] = {'P', 'C', 'V', 'C', 'K', 'P', 'T', '1'};
 
 CkptHeader ckpt_header_of(pcv_ctx ctx) {
@@ -984,6 +1003,7 @@ CkptHeader ckpt_header_of(pcv_ctx ctx) {
   h.b = m.b;
   h.Gb = m.Gb;
   h.S = m.S;
+  h.rhat_mode = m.rhat_mode;
   h.seed = (static_cast<uint64_t>(m.key1) << 32) | m.key0;
   h.chain_offset = m.chain_offset;
   h.n_warmup = m.n_warmup;
@@ -1001,9 +1021,10 @@ struct CkptArray {
 std::vector<CkptArray> ckpt_arrays(pcv_ctx ctx) {
   const DevModel& m = ctx->m;
   const size_t C = m.C, dC = static_cast<size_t>(m.d) * m.C, DC = static_cast<size_t>(m.D) * m.C;
-  return {{m.q0, 8 * dC},  {m.g0, 8 * dC}, {m.logp0, 8 * C}, {m.s0, 8 * C},     {m.Z, 8 * C},
-          {m.U, 8 * C},    {m.U2, 8 * C},  {m.V, 8 * C},     {m.V2, 8 * C},     {m.bmean, 8 * DC},
-          {m.bm2, 8 * DC}, {m.nacc, 8 * C}, {m.ndiv, 8 * C}};
+  const size_t K = static_cast<size_t>(m.K);
+  return {{m.q0, 8 * dC},  {m.g0, 8 * dC},   {m.logp0, 8 * C}, {m.s0, 8 * C},  {m.Z, 8 * C},
+          {m.U, 8 * C},    {m.U2, 8 * C},    {m.V, 8 * C},     {m.V2, 8 * C},  {m.bmean, 8 * DC},
+          {m.bm2, 8 * DC}, {m.nacc, 8 * C},  {m.ndiv, 8 * C},  {m.wsum, 8 * C}, {m.center, 8 * K}};
 }
 
 }  // namespace

@@ -170,6 +170,28 @@ __device__ __forceinline__ void chan_merge(double& n, double& mean, double& m2, 
   n = nt;
 }
 
+// Combine block statistics into a chain's.  Welford blocks (count, mean, M2)
+// Chan-merge.  Shifted-sum blocks (count, Y = sum (s - C_k), Y2 = sum
+// (s - C_k)^2) add, and block_finish turns the totals into the mean of
+// s - C_k and M2 = Y2 - Y^2 / n (the shift drops out of Rhat).
+__device__ __forceinline__ void block_merge(const DevModel& m, double& n, double& a, double& b, double nb,
+                                            double ab, double bb) {
+  if (m.rhat_mode == 1) {
+    n += nb;
+    a += ab;
+    b += bb;
+  } else {
+    chan_merge(n, a, b, nb, ab, bb);
+  }
+}
+__device__ __forceinline__ void block_finish(const DevModel& m, double n, double& a, double& b) {
+  if (m.rhat_mode == 1 && n > 0.0) {
+    const double y = a;
+    a = y / n;
+    b = b - y * y / n;
+  }
+}
+
 __device__ __forceinline__ double block_count(const DevModel& m, int64_t N, int dd) {
   const int64_t per = static_cast<int64_t>(m.Gb) * m.b;
   int64_t lo = dd * per, hi = (dd == m.D - 1) ? N : (dd + 1) * per;
@@ -234,14 +256,15 @@ __global__ void k_diag_fold(DevModel m, int64_t N, FoldDiag o) {
   o.sig2rel[k] = sig2rel;
   o.varrel[k] = sig2rel / LN;
   o.ess[k] = LN * s2rel / sig2rel;
-  // Rhat from Welford blocks
+  // Rhat from the blocks of each chain
   double cm[MAX_L], cm2[MAX_L];
   for (int l = 0; l < L; ++l) {
     double n = 0.0, mean = 0.0, m2 = 0.0;
     for (int dd = 0; dd < m.D; ++dd) {
       const int64_t off = static_cast<int64_t>(dd) * m.C + c0 + l;
-      chan_merge(n, mean, m2, block_count(m, N, dd), m.bmean[off], m.bm2[off]);
+      block_merge(m, n, mean, m2, block_count(m, N, dd), m.bmean[off], m.bm2[off]);
     }
+    block_finish(m, n, mean, m2);
     cm[l] = mean;
     cm2[l] = m2;
   }
@@ -297,12 +320,23 @@ __global__ void k_shuffle(DevModel m, int64_t N, int R, uint32_t s0, uint32_t s1
       int src = static_cast<int>(floor(uniform01(w.x, w.y) * L));
       if (src > L - 1) src = L - 1;
       const int64_t off = static_cast<int64_t>(dd) * m.C + static_cast<int64_t>(k) * L + src;
-      chan_merge(n, mean, m2, block_count(m, N, dd), m.bmean[off], m.bm2[off]);
+      block_merge(m, n, mean, m2, block_count(m, N, dd), m.bmean[off], m.bm2[off]);
     }
+    block_finish(m, n, mean, m2);
     cm[l] = mean;
     cm2[l] = m2;
   }
   rep[idx] = rhat_of(static_cast<double>(N), cm, cm2, L);
+}
+
+// Shifted sums, end of warm-up: C_k = (sum over the fold's chains of their
+// warm-up sums of s) / (L * N_wu).
+__global__ void k_center(DevModel m) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.K) return;
+  double t = 0.0;
+  for (int l = 0; l < m.L; ++l) t += m.wsum[static_cast<int64_t>(k) * m.L + l];
+  m.center[k] = m.n_warmup > 0 ? t / (static_cast<double>(m.L) * static_cast<double>(m.n_warmup)) : 0.0;
 }
 
 __global__ void k_shuffle_max(int K, int R, const double* rep, double* out) {
@@ -399,6 +433,11 @@ hipError_t launch_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uin
   hipLaunchKernelGGL(k_philox, dim3(nblocks(n)), dim3(TPB), 0, st, k0, k1, c0, c1, c2, c3, n, out);
   return hipGetLastError();
 }
+hipError_t launch_center(const DevModel& m, hipStream_t st) {
+  hipLaunchKernelGGL(k_center, dim3(nblocks(m.K, 64)), dim3(64), 0, st, m);
+  return hipGetLastError();
+}
+
 hipError_t launch_diag(const DevModel& m, int64_t N, double* fold_buf, double* out, hipStream_t st) {
   FoldDiag o;
   o.elpd = fold_buf;

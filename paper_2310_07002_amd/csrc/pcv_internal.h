@@ -50,9 +50,13 @@ struct DevModel {
   // chain state, [d][C] (chain index fastest)
   double *q0, *g0, *q1, *g1, *pm;
   double *logp0, *logp1, *s0, *h0;
-  // accumulators
+  // accumulators.  Block statistics: Welford mean and M2 of s, or with
+  // rhat_mode 1 (shifted sums) sum (s - C_k) and sum (s - C_k)^2
   double *Z, *U, *U2, *V, *V2, *bmean, *bm2;   // [C], [D][C]
   int64_t *nacc, *ndiv;
+  int rhat_mode;
+  double* wsum;     // [C] sum of warm-up draws of s (shifted sums)
+  double* center;   // [K] C_k, the fold's warm-up mean of s (shifted sums)
   // device-side transition counter (read when a kernel is given t < 0, so
   // one captured graph of a transition can be replayed)
   int64_t* t_dev;
@@ -244,7 +248,8 @@ __device__ __forceinline__ void leapfrog_update(const DevModel& m, int64_t c, in
   }
 }
 
-// Welford / log-sum-exp accumulation of post-warm-up draw i (Algorithm A2).
+// Welford (or shifted-sum) / log-sum-exp accumulation of post-warm-up draw i
+// (Algorithm A2).
 __device__ __forceinline__ void accumulate_draw(const DevModel& m, int64_t c, int64_t i, double s) {
   m.Z[c] = log_add_exp(m.Z[c], s);
   m.U2[c] = log_add_exp(m.U2[c], 2.0 * s);
@@ -253,11 +258,17 @@ __device__ __forceinline__ void accumulate_draw(const DevModel& m, int64_t c, in
   if (blk > m.D - 1) blk = m.D - 1;
   const double cnt = static_cast<double>(i - blk * per_block + 1);
   const int64_t o = blk * m.C + c;
-  const double mean = m.bmean[o];
-  const double delta = s - mean;
-  const double nm = mean + delta / cnt;
-  m.bmean[o] = nm;
-  m.bm2[o] += delta * (s - nm);
+  if (m.rhat_mode == 1) {
+    const double dv = s - m.center[c / m.L];
+    m.bmean[o] += dv;
+    m.bm2[o] += dv * dv;
+  } else {
+    const double mean = m.bmean[o];
+    const double delta = s - mean;
+    const double nm = mean + delta / cnt;
+    m.bmean[o] = nm;
+    m.bm2[o] += delta * (s - nm);
+  }
   if ((i + 1) % m.b == 0) {
     const double z = m.Z[c];
     const double lb = log(static_cast<double>(m.b));
@@ -294,7 +305,9 @@ __device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
     m.logp0[c] = m.logp1[c];
     m.s0[c] = log_pred_fold<FAM>(m, m.q0, c);
   }
-  if (t >= m.n_warmup) {
+  if (t < m.n_warmup) {
+    if (m.rhat_mode == 1) m.wsum[c] += m.s0[c];
+  } else {
     accumulate_draw(m, c, t - m.n_warmup, m.s0[c]);
     m.nacc[c] += accepted ? 1 : 0;
     m.ndiv[c] += divergent ? 1 : 0;

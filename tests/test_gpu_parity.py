@@ -220,6 +220,40 @@ def test_fp64_run_replays_oracle_c1(dev):
     np.testing.assert_allclose(rep_g, rep_o, rtol=1e-9)
 
 
+def test_shifted_sums_rhat_replays_oracle(dev):
+    """rhat_mode = shifted sums (Algorithm A2): the fold centres are fixed when
+    the warm-up ends (here inside a pcv_step call), then the device's block
+    sums, Rhat and block-shuffle benchmark follow the oracle's."""
+    w = dataclasses.replace(W.fold_subset(W.make("c1"), 0, 30), n_warmup=60, rhat_mode=1)
+    run = sampler.run_all(w, n_iter=260)
+    s = binding.PCV.from_workload(w)
+    for n in (37, 100, 123):
+        s.step(n)
+    acc = s.get_accumulators(w.n_blocks)
+    np.testing.assert_allclose(acc["blk_mean"], run.acc.blk_mean, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(acc["blk_m2"], run.acc.blk_m2, rtol=1e-9, atol=1e-9)
+    d = s.diagnostics()
+    o = diagnostics.from_accumulators(run.acc, w.K, w.L, w.batch_size)
+    np.testing.assert_allclose(d["rhat_fold"], o["rhat_fold"], rtol=1e-9)
+    rep_g = s.shuffle_benchmark(20, seed=5)
+    _, rep_o = diagnostics.shuffle_benchmark(run.acc, w.K, w.L, w.n_blocks, 20, seed=5)
+    np.testing.assert_allclose(rep_g, rep_o, rtol=1e-9)
+
+
+def test_shifted_sums_equal_welford_on_matrix_cores(dev):
+    w = dataclasses.replace(W.fold_subset(W.make("c4"), 0, 30), n_warmup=20, batch_size=10)
+    a = binding.PCV.from_workload(w, precision=W.PREC_BF16X3, rhat_mode=binding.RHAT_WELFORD)
+    b = binding.PCV.from_workload(w, precision=W.PREC_BF16X3, rhat_mode=binding.RHAT_SHIFTED_SUMS)
+    for x in (a, b):
+        x.step(15)
+        x.step(60)
+    np.testing.assert_array_equal(a.get_state()[0], b.get_state()[0])
+    da, db = a.diagnostics(), b.diagnostics()
+    assert da["elpd"] == db["elpd"]
+    np.testing.assert_allclose(db["rhat_fold"], da["rhat_fold"], rtol=1e-9)
+    np.testing.assert_allclose(b.shuffle_benchmark(10, seed=2), a.shuffle_benchmark(10, seed=2), rtol=1e-9)
+
+
 def test_fp64_run_replays_oracle_hvblock(dev):
     w = dataclasses.replace(W.fold_subset(W.make("c3"), 0, 25), n_warmup=40)
     _say("[replay] c3 fp64 subset 120 iterations")
@@ -327,13 +361,17 @@ def test_design_as_bf16_planes_matches_fp64_design(dev, tmp_path):
         np.testing.assert_array_equal(x, y)
 
 
-@pytest.mark.parametrize("name,prec,folds_", [("c1", "fp64", (0, 12)), ("c4", "bf16x3", (0, 40))])
-def test_checkpoint_resume_is_exact(dev, tmp_path, name, prec, folds_):
+@pytest.mark.parametrize("name,prec,folds_,mode", [("c1", "fp64", (0, 12), 0), ("c4", "bf16x3", (0, 40), 0),
+                                                  ("c1", "fp64", (0, 12), 1)])
+def test_checkpoint_resume_is_exact(dev, tmp_path, name, prec, folds_, mode):
     """Run A: 30 transitions, save, 25 more.  Run B: a fresh context loads the
     checkpoint and runs 25.  Everything must agree bit for bit (random
-    numbers are keyed by chain and transition).  Checkpoints of another run
-    and damaged files are refused and leave the context usable."""
-    w = dataclasses.replace(W.fold_subset(W.make(name), *folds_), n_warmup=12, batch_size=4)
+    numbers are keyed by chain and transition).  With shifted sums the save
+    falls inside the warm-up, so the resumed run fixes the fold centres from
+    restored warm-up sums.  Checkpoints of another run and damaged files are
+    refused and leave the context usable."""
+    w = dataclasses.replace(W.fold_subset(W.make(name), *folds_), n_warmup=40 if mode else 12,
+                            batch_size=4, rhat_mode=mode)
     path = str(tmp_path / "run.ckpt")
     _say(f"[checkpoint] {name} {prec} C={w.C}")
     a = binding.PCV.from_workload(w, precision=PREC[prec])
