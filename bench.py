@@ -20,7 +20,7 @@ Also reported on the same JSON line:
                 the same workload, a few steps, and the speedup over it
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5]
        [--precision bf16x3|bf16x5|fp64|fp32|fp64u] [--no-cpu-baseline]
-       [--no-plain-fp64] [--time-to-rhat]
+       [--no-plain-fp64] [--time-to-rhat] [--no-autotune]
 """
 from __future__ import annotations
 
@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--no-plain-fp64", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--time-to-rhat", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the analytic launch shape instead of timing candidates first")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device-to-device copy first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -137,6 +139,14 @@ def main():
     stream = torch.cuda.current_stream()
     log(f"bench: init {workload_label(w, prec)}")
     s = binding.PCV.from_workload(w, precision=PREC_NAMES[prec], stream=stream)
+    tune = None
+    if not args.no_autotune and prec != "fp64u":
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        tune = s.autotune()
+        tune["seconds"] = time.perf_counter() - ta
+        tune["knob"] = "row splits per chain tile" if prec.startswith("bf16") else "waves per workgroup"
+        log(f"bench: autotune chose {tune['knob']} = {tune['config']} ({tune['ms']:.4f} ms) in {tune['seconds']:.2f} s")
     s.step(args.warmup)
     torch.cuda.synchronize()
     s.timing_read(reset=True)
@@ -184,6 +194,8 @@ def main():
             "config": {"workload": workload_label(w, prec), "folds": w.K, "chains_per_fold": w.L,
                        "chains": w.C, "leapfrog_steps": w.n_leapfrog, "parallelism": "single GPU"},
             "roofline": roofline}
+    if tune is not None:
+        line["autotune"] = tune
 
     d = s.diagnostics() if args.warmup + args.steps > w.n_warmup + 1 else None
     s.close()
@@ -210,6 +222,8 @@ def main():
     if args.time_to_rhat:
         log("bench: full run for wall time to Rhat_max < 1.01")
         r = binding.PCV.from_workload(w, precision=PREC_NAMES[prec], stream=stream)
+        if tune is not None:
+            r.autotune()              # tuning is reported separately, outside the clock
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r.step(w.n_warmup)

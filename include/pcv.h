@@ -219,6 +219,24 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
                                 double* V2, double* blk_mean, double* blk_m2,
                                 int64_t* n_accept, int64_t* n_divergent);
 
+/* Autotuner for the hot kernel's launch shape.  It times candidate shapes of
+ * the gradient kernel:
+ * - matrix-core path: the number of row splits per 256-chain tile, around
+ *   the analytic choice made at init;
+ * - fused VALU path: waves per workgroup, each owning a range of rows.
+ * Timing runs on a scratch copy of the current positions, so the chains are
+ * untouched.  The fastest shape is kept, and the captured transition graph is
+ * rebuilt on the next pcv_step.
+ * cache_path (or NULL) names a JSON file of tuned shapes, keyed by path,
+ * family, precision, fold encoding, sizes and GPU architecture.  A hit is
+ * applied without timing; a miss is timed and written back (created,
+ * updated or extended).
+ * config receives the shape (split count or waves); ms receives its mean
+ * kernel time (both optional).  Synchronises.
+ * Errors: PCV_ERR_UNSUPPORTED on the plain fp64 path; PCV_ERR_INVALID_ARG if
+ * the cache cannot be written; PCV_ERR_DEVICE. */
+pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, double* ms);
+
 /* Checkpoint and resume.  pcv_save writes everything a run carries between
  * transitions to the file `path`:
  * - the accepted positions, gradients, log pi and log predictive of every chain;

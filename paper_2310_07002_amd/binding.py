@@ -24,8 +24,8 @@ STATUS_NAMES = {0: "PCV_OK", 1: "PCV_ERR_INVALID_ARG", 2: "PCV_ERR_NOMEM", 3: "P
 EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_elpd",
             "pcv_shuffle_benchmark", "pcv_destroy", "pcv_last_error", "pcv_status_str",
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
-            "pcv_get_accumulators", "pcv_save", "pcv_load", "pcv_philox", "pcv_timing_enable",
-            "pcv_timing_read"]
+            "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
+            "pcv_timing_enable", "pcv_timing_read"]
 
 
 class PcvError(RuntimeError):
@@ -98,6 +98,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_get_state": ([P, dp, dp, dp], I32),
         "pcv_set_state": ([P, dp], I32),
         "pcv_get_accumulators": ([P, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
+        "pcv_autotune": ([P, ctypes.c_char_p, ctypes.POINTER(I32), dp], I32),
         "pcv_save": ([P, ctypes.c_char_p], I32),
         "pcv_load": ([P, ctypes.c_char_p], I32),
         "pcv_philox": ([U64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, I64,
@@ -318,6 +319,16 @@ class PCV:
         out["blk_mean"] = out["blk_mean"].reshape(n_blocks, C).T.copy()
         out["blk_m2"] = out["blk_m2"].reshape(n_blocks, C).T.copy()
         return out
+
+    def autotune(self, cache_path: Optional[str] = None) -> dict:
+        """Time candidate launch shapes of the hot kernel and keep the fastest
+        (row splits on the matrix-core path, waves per workgroup on the fused
+        VALU path); cache_path: JSON cache of tuned shapes."""
+        cfg = ctypes.c_int32()
+        ms = ctypes.c_double()
+        self._check(self._lib.pcv_autotune(self._ctx, os.fsencode(cache_path) if cache_path else None,
+                                           ctypes.byref(cfg), ctypes.byref(ms)), "pcv_autotune")
+        return {"config": cfg.value, "ms": ms.value}
 
     def save(self, path: str):
         """Checkpoint the run (state, accumulators, transition count) to `path`."""

@@ -93,6 +93,8 @@ struct pcv_ctx_s {
   std::string err;
   bool dead = false;
   uint64_t fingerprint = 0;   // of X, y, folds and groups (checkpoints)
+  std::vector<int32_t> group_of_host;   // HIER: groups (VALU partitions when autotuning)
+  int split_cap = 0;                    // MFMA: row splits the partial buffers hold
 };
 
 namespace {
@@ -291,6 +293,28 @@ pcv_status capture_transition(pcv_ctx ctx) {
   ctx->graph = g;
   CK(hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
   return PCV_OK;
+}
+
+// Row ranges [wr[w], wr[w+1]) of the W waves of a fused-VALU workgroup.  For
+// the hierarchical family the cuts are moved to group starts so each group
+// has one owner wave.
+std::vector<int32_t> valu_partition(int64_t n, int W, const int32_t* group_of) {
+  std::vector<int32_t> wr(W + 1);
+  for (int w = 0; w <= W; ++w) wr[w] = static_cast<int32_t>(n * w / W);
+  if (group_of) {
+    for (int w = 1; w < W; ++w) {
+      int64_t i = std::max<int64_t>(wr[w], wr[w - 1]);
+      while (i > wr[w - 1] && i < n && group_of[i] == group_of[i - 1]) --i;
+      if (i <= wr[w - 1]) {
+        i = std::max<int64_t>(wr[w], wr[w - 1]);
+        while (i < n && i > 0 && group_of[i] == group_of[i - 1]) ++i;
+      }
+      wr[w] = static_cast<int32_t>(std::min<int64_t>(i, n));
+    }
+    for (int w = 1; w <= W; ++w) wr[w] = std::max(wr[w], wr[w - 1]);
+    wr[W] = static_cast<int32_t>(n);
+  }
+  return wr;
 }
 
 bool finite_all(const double* a, int64_t n) {
@@ -598,22 +622,10 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     if (valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536)
       return fail(ctx, PCV_ERR_UNSUPPORTED, "too many groups for the fused path");
     ctx->W = W;
-    std::vector<int32_t> wr(W + 1);
-    for (int w = 0; w <= W; ++w) wr[w] = static_cast<int32_t>(n * w / W);
-    if (hier) {  // align row ranges to group starts so each group has one owner wave
-      for (int w = 1; w < W; ++w) {
-        int64_t i = std::max<int64_t>(wr[w], wr[w - 1]);
-        while (i > wr[w - 1] && i < n && md->group_of[i] == md->group_of[i - 1]) --i;
-        if (i <= wr[w - 1]) {
-          i = std::max<int64_t>(wr[w], wr[w - 1]);
-          while (i < n && i > 0 && md->group_of[i] == md->group_of[i - 1]) ++i;
-        }
-        wr[w] = static_cast<int32_t>(std::min<int64_t>(i, n));
-      }
-      for (int w = 1; w <= W; ++w) wr[w] = std::max(wr[w], wr[w - 1]);
-      wr[W] = static_cast<int32_t>(n);
-    }
-    TRY(upload(ctx, &ctx->wave_rows, wr.data(), wr.size()));
+    if (hier) ctx->group_of_host.assign(md->group_of, md->group_of + n);
+    const std::vector<int32_t> wr = valu_partition(n, W, hier ? md->group_of : nullptr);
+    TRY(dalloc(ctx, &ctx->wave_rows, 9));   // room for any W <= 8 (autotuning)
+    CK(hipMemcpy(ctx->wave_rows, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice));
     m.wave_rows = ctx->wave_rows;
   } else if (ctx->path == PATH_MFMA) {
     const int R = mfma_rows_per_tile();
@@ -654,6 +666,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     double* vp;
     TRY(dalloc(ctx, &vp, static_cast<size_t>(ctx->n_splits) * C));
     ctx->Vpart = vp;
+    ctx->split_cap = ctx->n_splits;
   } else {
     if (rocblas_create_handle(&ctx->rb) != rocblas_status_success)
       return fail(ctx, PCV_ERR_DEVICE, "rocblas_create_handle failed");
@@ -1098,6 +1111,203 @@ pcv_status pcv_load(pcv_ctx ctx, const char* path) {
     off += a.bytes;
   }
   ctx->t = h.t;
+  return PCV_OK;
+}
+
+// ---- autotuning ------------------------------------------------------------
+
+namespace {
+
+std::string tune_key(pcv_ctx ctx) {
+  const DevModel& m = ctx->m;
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "%s fam=%d prec=%d folds=%d n=%lld p=%lld C=%lld K=%d L=%d groups=%d arch=%s",
+                ctx->path == PATH_MFMA ? "mfma" : "valu", m.family, ctx->prec, m.fold_kind,
+                static_cast<long long>(m.n), static_cast<long long>(m.p), static_cast<long long>(m.C), m.K, m.L,
+                m.n_groups, arch.c_str());
+  return buf;
+}
+
+// The cache is a flat JSON object, one entry per line:
+//   "<key>": {"cfg": <int>, "ms": <float>},
+struct TuneEntry {
+  std::string key;
+  int cfg;
+  double ms;
+};
+
+std::vector<TuneEntry> cache_read(const char* path) {
+  std::vector<TuneEntry> out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  char line[2048];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* q1 = std::strchr(line, '"');
+    if (!q1) continue;
+    const char* q2 = std::strchr(q1 + 1, '"');
+    if (!q2) continue;
+    const char* c = std::strstr(q2, "\"cfg\":");
+    const char* t = std::strstr(q2, "\"ms\":");
+    TuneEntry e{std::string(q1 + 1, q2), 0, 0.0};
+    if (c && t && std::sscanf(c + 6, "%d", &e.cfg) == 1 && std::sscanf(t + 5, "%lf", &e.ms) == 1) out.push_back(e);
+  }
+  std::fclose(f);
+  return out;
+}
+
+bool cache_write(const char* path, const std::vector<TuneEntry>& entries) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  bool ok = std::fprintf(f, "{\n") > 0;
+  for (size_t i = 0; i < entries.size(); ++i)
+    ok = ok && std::fprintf(f, "  \"%s\": {\"cfg\": %d, \"ms\": %.9g}%s\n", entries[i].key.c_str(), entries[i].cfg,
+                            entries[i].ms, i + 1 < entries.size() ? "," : "") > 0;
+  ok = ok && std::fprintf(f, "}\n") > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return false;
+  }
+  return true;
+}
+
+void drop_graph(pcv_ctx ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+}
+
+// MFMA path: ns row splits per chain tile (the partial buffers grow if needed).
+pcv_status apply_splits(pcv_ctx ctx, int ns) {
+  const int tps = (ctx->n_tiles + ns - 1) / ns;
+  const int nsp = (ctx->n_tiles + tps - 1) / tps;
+  if (nsp > ctx->split_cap) {
+    float* g;
+    double* v;
+    TRY(dalloc(ctx, &g, static_cast<size_t>(nsp) * ctx->m.p * ctx->m.C));
+    TRY(dalloc(ctx, &v, static_cast<size_t>(nsp) * ctx->m.C));
+    ctx->Gpart = g;
+    ctx->Vpart = v;
+    ctx->split_cap = nsp;
+  }
+  ctx->tiles_per_split = tps;
+  ctx->n_splits = nsp;
+  drop_graph(ctx);
+  return PCV_OK;
+}
+
+bool waves_ok(pcv_ctx ctx, int W) {
+  return W >= 1 && W <= 8 && !(ctx->pb >= 32 && W > 4) && ctx->m.n / W >= 8 &&
+         valu_smem_bytes(ctx->fp64, W, ctx->m.family, ctx->m.n_groups) <= 65536;
+}
+
+// VALU path: W waves per workgroup, each owning a range of rows.
+pcv_status apply_waves(pcv_ctx ctx, int W) {
+  const std::vector<int32_t> wr =
+      valu_partition(ctx->m.n, W, ctx->group_of_host.empty() ? nullptr : ctx->group_of_host.data());
+  CK(hipMemcpy(ctx->wave_rows, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice));
+  ctx->W = W;
+  return PCV_OK;
+}
+
+// Mean time of the hot kernel: gradient launches at q1 (a copy of the chain
+// positions; q1 is per-trajectory scratch, so the chains are untouched).
+pcv_status time_hot(pcv_ctx ctx, int reps, double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  CK(hipEventCreate(&a));
+  CK(hipEventCreate(&b));
+  auto launch = [&]() -> pcv_status {
+    if (ctx->path == PATH_VALU) {
+      CK(launch_valu(ctx->m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, 1, 0, 0, 0, ctx->st));
+      return PCV_OK;
+    }
+    return split_partials(ctx, false);
+  };
+  pcv_status s = launch();
+  if (s == PCV_OK && hipEventRecord(a, ctx->st) != hipSuccess) s = PCV_ERR_DEVICE;
+  for (int r = 0; r < reps && s == PCV_OK; ++r) s = launch();
+  if (s == PCV_OK && hipEventRecord(b, ctx->st) != hipSuccess) s = PCV_ERR_DEVICE;
+  if (s == PCV_OK && hipEventSynchronize(b) != hipSuccess) s = PCV_ERR_DEVICE;
+  float t = 0.f;
+  if (s == PCV_OK && hipEventElapsedTime(&t, a, b) != hipSuccess) s = PCV_ERR_DEVICE;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (s != PCV_OK) return fail(ctx, PCV_ERR_DEVICE, "autotune timing failed");
+  *ms = static_cast<double>(t) / reps;
+  return PCV_OK;
+}
+
+}  // namespace
+
+pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, double* ms) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (ctx->path == PATH_UNFUSED) return fail(ctx, PCV_ERR_UNSUPPORTED, "the plain fp64 path has nothing to tune");
+  const std::string key = tune_key(ctx);
+  std::vector<TuneEntry> cache = cache_path ? cache_read(cache_path) : std::vector<TuneEntry>{};
+  for (const TuneEntry& e : cache) {
+    if (e.key != key) continue;
+    const bool valid = ctx->path == PATH_MFMA ? (e.cfg >= 1 && e.cfg <= ctx->n_tiles) : waves_ok(ctx, e.cfg);
+    if (!valid) break;   // stale entry: tune again
+    if (ctx->path == PATH_MFMA) TRY(apply_splits(ctx, e.cfg));
+    else TRY(apply_waves(ctx, e.cfg));
+    if (config) *config = e.cfg;
+    if (ms) *ms = e.ms;
+    return PCV_OK;
+  }
+  std::vector<int> cand;
+  if (ctx->path == PATH_MFMA) {
+    const int ns0 = ctx->n_splits, hi = std::min(64, ctx->n_tiles);
+    for (int ns : {ns0 / 2, ns0 - 2, ns0 - 1, ns0, ns0 + 1, ns0 + 2, 2 * ns0}) {
+      if (ns < 1 || ns > hi) continue;
+      const int tps = (ctx->n_tiles + ns - 1) / ns;
+      const int nsp = (ctx->n_tiles + tps - 1) / tps;
+      if (std::find(cand.begin(), cand.end(), nsp) == cand.end()) cand.push_back(nsp);
+    }
+  } else {
+    for (int W : {1, 2, 4, 8})
+      if (waves_ok(ctx, W)) cand.push_back(W);
+  }
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  CK(hipMemcpyAsync(ctx->m.q1, ctx->m.q0, sizeof(double) * ctx->m.d * ctx->m.C, hipMemcpyDeviceToDevice,
+                    ctx->st));
+  const int reps = ctx->path == PATH_MFMA ? 3 : 5;
+  int best = -1;
+  double best_ms = 0.0;
+  pcv_status s = PCV_OK;
+  for (int c : cand) {
+    s = ctx->path == PATH_MFMA ? apply_splits(ctx, c) : apply_waves(ctx, c);
+    double t = 0.0;
+    if (s == PCV_OK) s = time_hot(ctx, reps, &t);
+    if (s != PCV_OK) break;
+    if (best < 0 || t < best_ms) {
+      best = c;
+      best_ms = t;
+    }
+  }
+  ctx->timing = timing;
+  if (s != PCV_OK) return s;
+  TRY(ctx->path == PATH_MFMA ? apply_splits(ctx, best) : apply_waves(ctx, best));
+  if (config) *config = best;
+  if (ms) *ms = best_ms;
+  if (cache_path) {
+    bool replaced = false;
+    for (TuneEntry& e : cache)
+      if (e.key == key) {
+        e.cfg = best;
+        e.ms = best_ms;
+        replaced = true;
+      }
+    if (!replaced) cache.push_back({key, best, best_ms});
+    if (!cache_write(cache_path, cache))
+      return fail(ctx, PCV_ERR_INVALID_ARG, std::string("cannot write the tuning cache ") + cache_path);
+  }
   return PCV_OK;
 }
 

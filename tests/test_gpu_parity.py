@@ -343,6 +343,37 @@ def test_state_roundtrip_and_divergence_counting(dev):
     np.testing.assert_allclose(lp1, lp0, rtol=1e-15)
 
 
+@pytest.mark.parametrize("name,prec,folds_,tol_v,tol_g", [("c1", "fp64", None, 1e-12, 1e-12),
+                                                        ("c2", "fp32", None, 1e-5, 1e-5),
+                                                        ("c4", "bf16x3", (0, 64), 1e-5, 5e-5)])
+def test_autotune_keeps_parity_and_caches(dev, tmp_path, name, prec, folds_, tol_v, tol_g):
+    """The tuned launch shape changes only the order of sums: the log density
+    and gradient still match the oracle, the shape is cached in JSON, a second
+    context takes it from the cache, and the sampler steps with it."""
+    import json
+    w = W.make(name)
+    if folds_:
+        w = W.fold_subset(w, *folds_)
+    cache = str(tmp_path / "tune.json")
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    r = s.autotune(cache)
+    _say(f"[autotune] {name} {prec}: config {r['config']} {r['ms']:.4f} ms")
+    assert r["config"] >= 1 and r["ms"] > 0
+    theta = _theta_near_init(w, seed=7)
+    lp_o, g_o = _oracle_eval(w, theta)
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    assert (np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)).max() < tol_v
+    assert _normwise(g.cpu().numpy(), g_o).max() < tol_g
+    entries = json.load(open(cache))
+    assert len(entries) == 1 and list(entries.values())[0]["cfg"] == r["config"]
+    s2 = binding.PCV.from_workload(w, precision=PREC[prec])
+    r2 = s2.autotune(cache)
+    assert r2["config"] == r["config"] and r2["ms"] == pytest.approx(r["ms"], rel=1e-6)
+    s2.step(3)
+    th, lp2, _ = s2.get_state()
+    assert np.isfinite(th).all() and np.isfinite(lp2).all()
+
+
 def test_design_as_bf16_planes_matches_fp64_design(dev, tmp_path):
     """X handed over as its stored bf16 hi/lo planes is the same design as its
     fp64 sum: identical results, and checkpoints are interchangeable."""
