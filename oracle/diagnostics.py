@@ -211,3 +211,27 @@ def shuffle_benchmark(acc, K: int, L: int, D: int, R: int, seed: int, fold_offse
                                               bm[k, src, dd], b2[k, src, dd])
             out[k, r] = rhat_from_moments(N, mean, m2)
     return out, out.max(axis=0)
+
+
+def compare(elpd_fold_a, mcse_fold_a, elpd_fold_b, mcse_fold_b) -> dict:
+    """Pairwise comparison of models A and B evaluated on the same folds.
+
+      Delta_k  = S_A,k - S_B,k,   Delta = sum_k Delta_k                       (eq sel-cv)
+      sigma2   = 1/(K-1) sum_k (Delta_k - Delta/K)^2
+      Pr(A > B) ~ Phi(Delta / sqrt(K sigma2))                                  (eq norm-approx)
+      MCSE(Delta)^2 = sum over both models and all folds of MCSE(S_M,k)^2      (eq mc-var)
+
+    Reading: with Delta = 0 and sigma2 = 0 the ratio is undefined; it is taken
+    as Pr = 1/2 (no evidence either way), and sigma2 = 0 with Delta != 0 gives
+    Pr = 1 or 0 by the sign of Delta.
+    """
+    dk = np.asarray(elpd_fold_a, dtype=np.float64) - np.asarray(elpd_fold_b, dtype=np.float64)
+    K = dk.size
+    delta = float(np.sum(dk))
+    sigma2 = float(np.sum((dk - delta / K) ** 2) / (K - 1)) if K > 1 else float("nan")
+    if sigma2 > 0:
+        prob = 0.5 * math.erfc(-delta / math.sqrt(2.0 * K * sigma2))
+    else:
+        prob = 0.5 if delta == 0 else (1.0 if delta > 0 else 0.0)
+    mcse = math.sqrt(float(np.sum(np.square(mcse_fold_a)) + np.sum(np.square(mcse_fold_b))))
+    return {"delta": delta, "delta_fold": dk, "sigma2": sigma2, "prob_a_better": prob, "mcse": mcse}

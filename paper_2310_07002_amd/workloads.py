@@ -364,6 +364,27 @@ def fold_subset(w: Workload, k0: int, k1: int) -> Workload:
     return sub
 
 
+def drop_covariates(w: Workload, cols) -> Workload:
+    """The same workload for the model without covariates `cols` (GLM
+    families): the nested-model comparison of Section 2.3, model B missing
+    covariates of model A.  Same folds, rows and random streams; the prior
+    scales, mass-matrix entries and initial positions of the kept covariates
+    are those of the full model."""
+    assert w.family in (GAUSSIAN, LOGISTIC, POISSON), "GLM families only"
+    keep = np.setdiff1d(np.arange(w.p), np.asarray(cols))
+    sub = dataclasses.replace(w)
+    sub.name = w.name + "_minus_" + "_".join(str(int(c)) for c in np.atleast_1d(cols))
+    sub.X = np.ascontiguousarray(w.X[:, keep])
+    if w.x_hi is not None:
+        sub.x_hi = np.ascontiguousarray(w.x_hi[:, keep])
+        sub.x_lo = np.ascontiguousarray(w.x_lo[:, keep])
+    sub.prior_scale = None if w.prior_scale is None else w.prior_scale[keep].copy()
+    sub.inv_mass = w.inv_mass[keep].copy()
+    sub.init_pos = np.ascontiguousarray(w.init_pos[:, keep])
+    sub.truth = None if w.truth is None else np.asarray(w.truth)[keep].copy()
+    return sub
+
+
 def with_dense_roles(w: Workload) -> Workload:
     """Same workload with its folds given as a dense K x n role matrix."""
     roles = np.full((w.K, w.n), ROLE_TRAIN, dtype=np.int8)
