@@ -137,6 +137,17 @@ typedef struct pcv_diag {
   double* ess_fold;       /* optional, K entries, caller-owned                      */
 } pcv_diag;
 
+/* Comparison of two models on the same folds (Sections 2.3 and 4.1). */
+typedef struct pcv_comparison {
+  double delta;           /* Delta = sum_k Delta_k, Delta_k = S_A,k - S_B,k (eq sel-cv) */
+  double sigma2;          /* sample variance of the Delta_k, 1/(K-1) sum (Delta_k - Delta/K)^2 */
+  double prob_a_better;   /* Pr(M_A better than M_B | y) ~ Phi(Delta / sqrt(K sigma2))
+                             (eq norm-approx); 1/2 when Delta = sigma2 = 0            */
+  double mcse;            /* Monte Carlo s.e. of Delta: both models' fold variances
+                             add (eq mc-var)                                          */
+  double* delta_fold;     /* optional, K entries, caller-owned                        */
+} pcv_comparison;
+
 typedef struct pcv_ctx_s* pcv_ctx;
 
 /* Validate the model and data, copy them to the device, and evaluate log pi,
@@ -180,6 +191,14 @@ pcv_status pcv_elpd(pcv_ctx ctx, double* elpd, double* mcse, double* elpd_fold, 
  * Synchronises.  PCV_ERR_STATE before 2 draws, PCV_ERR_INVALID_ARG if R < 1. */
 pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* rhat_max_rep,
                                  double* rhat_rep);
+
+/* Pairwise model comparison from two runs on the same folds (same fold
+ * encoding and arrays, checked by fingerprint): context a holds model A,
+ * context b model B, for instance nested designs that differ by a covariate
+ * (Section 2.3).  Both need post-warm-up draws.  Synchronises both streams.
+ * Errors: PCV_ERR_INVALID_ARG for a null output or different fold sets
+ * (message on a); PCV_ERR_STATE when either run has no draw yet. */
+pcv_status pcv_compare(pcv_ctx a, pcv_ctx b, pcv_comparison* out);
 
 void pcv_destroy(pcv_ctx ctx);
 const char* pcv_last_error(pcv_ctx ctx);

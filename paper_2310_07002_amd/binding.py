@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "PCV_OK", 1: "PCV_ERR_INVALID_ARG", 2: "PCV_ERR_NOMEM", 3: "P
                 4: "PCV_ERR_STATE", 5: "PCV_ERR_UNSUPPORTED"}
 
 EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_elpd",
-            "pcv_shuffle_benchmark", "pcv_destroy", "pcv_last_error", "pcv_status_str",
+            "pcv_shuffle_benchmark", "pcv_compare", "pcv_destroy", "pcv_last_error", "pcv_status_str",
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
             "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
             "pcv_timing_enable", "pcv_timing_read"]
@@ -59,6 +59,12 @@ X_FP64, X_BF16_HILO = 0, 1
 RHAT_WELFORD, RHAT_SHIFTED_SUMS = 0, 1
 
 
+class pcv_comparison(ctypes.Structure):
+    _fields_ = [("delta", ctypes.c_double), ("sigma2", ctypes.c_double),
+                ("prob_a_better", ctypes.c_double), ("mcse", ctypes.c_double),
+                ("delta_fold", ctypes.POINTER(ctypes.c_double))]
+
+
 class pcv_diag(ctypes.Structure):
     _fields_ = [("rhat_max", ctypes.c_double), ("ess", ctypes.c_double),
                 ("elpd", ctypes.c_double), ("mcse", ctypes.c_double),
@@ -90,6 +96,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_diagnostics": ([P, ctypes.POINTER(pcv_diag)], I32),
         "pcv_elpd": ([P, dp, dp, dp, dp], I32),
         "pcv_shuffle_benchmark": ([P, I32, U64, dp, dp], I32),
+        "pcv_compare": ([P, P, ctypes.POINTER(pcv_comparison)], I32),
         "pcv_destroy": ([P], None),
         "pcv_last_error": ([P], ctypes.c_char_p),
         "pcv_status_str": ([I32], ctypes.c_char_p),
@@ -319,6 +326,15 @@ class PCV:
         out["blk_mean"] = out["blk_mean"].reshape(n_blocks, C).T.copy()
         out["blk_m2"] = out["blk_m2"].reshape(n_blocks, C).T.copy()
         return out
+
+    def compare(self, other: "PCV") -> dict:
+        """This run as model A against `other` as model B on the same folds."""
+        df = np.zeros(self.K)
+        out = pcv_comparison()
+        out.delta_fold = _dptr(df)
+        self._check(self._lib.pcv_compare(self._ctx, other._ctx, ctypes.byref(out)), "pcv_compare")
+        return {"delta": out.delta, "sigma2": out.sigma2, "prob_a_better": out.prob_a_better,
+                "mcse": out.mcse, "delta_fold": df}
 
     def autotune(self, cache_path: Optional[str] = None) -> dict:
         """Time candidate launch shapes of the hot kernel and keep the fastest

@@ -93,6 +93,7 @@ struct pcv_ctx_s {
   std::string err;
   bool dead = false;
   uint64_t fingerprint = 0;   // of X, y, folds and groups (checkpoints)
+  uint64_t fold_fp = 0;       // of the fold set alone (model comparison)
   std::vector<int32_t> group_of_host;   // HIER: groups (VALU partitions when autotuning)
   int split_cap = 0;                    // MFMA: row splits the partial buffers hold
 };
@@ -469,6 +470,13 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     if (fm->kind == PCV_FOLDS_DENSE) h = fp_mix(h, fm->roles, static_cast<size_t>(K) * static_cast<size_t>(n));
     if (hier) h = fp_mix(h, md->group_of, sizeof(int32_t) * static_cast<size_t>(n));
     ctx->fingerprint = h;
+    uint64_t f = 0xcbf29ce484222325ULL;
+    const int64_t shape[3] = {fm->kind, n, K};
+    f = fp_mix(f, shape, sizeof shape);
+    if (fm->kind == PCV_FOLDS_INDEX) f = fp_mix(f, fm->fold_index, sizeof(int32_t) * static_cast<size_t>(n));
+    if (fm->kind == PCV_FOLDS_INTERVALS) f = fp_mix(f, fm->intervals, sizeof(int64_t) * 4 * static_cast<size_t>(K));
+    if (fm->kind == PCV_FOLDS_DENSE) f = fp_mix(f, fm->roles, static_cast<size_t>(K) * static_cast<size_t>(n));
+    ctx->fold_fp = f;
   }
   if (md->precision == PCV_PREC_FP64 || md->precision == PCV_PREC_FP32) {
     ctx->path = PATH_VALU;
@@ -1111,6 +1119,43 @@ pcv_status pcv_load(pcv_ctx ctx, const char* path) {
     off += a.bytes;
   }
   ctx->t = h.t;
+  return PCV_OK;
+}
+
+// ---- model comparison --------------------------------------------------------
+
+pcv_status pcv_compare(pcv_ctx a, pcv_ctx b, pcv_comparison* out) {
+  if (!usable(a) || !usable(b)) return PCV_ERR_STATE;
+  if (!out) return fail(a, PCV_ERR_INVALID_ARG, "null output");
+  if (a->m.K != b->m.K || a->fold_fp != b->fold_fp)
+    return fail(a, PCV_ERR_INVALID_ARG, "the two models were not evaluated on the same folds");
+  const int K = a->m.K;
+  std::vector<double> ea(K), ma(K), eb(K), mb(K);
+  double ta = 0.0, sa = 0.0, tb = 0.0, sb = 0.0;
+  pcv_status st = pcv_elpd(a, &ta, &sa, ea.data(), ma.data());
+  if (st != PCV_OK) return st;
+  st = pcv_elpd(b, &tb, &sb, eb.data(), mb.data());
+  if (st != PCV_OK) return fail(a, st, std::string("model B: ") + b->err);
+  double delta = 0.0, var_mc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    delta += ea[k] - eb[k];
+    var_mc += ma[k] * ma[k] + mb[k] * mb[k];
+  }
+  double ss = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double e = (ea[k] - eb[k]) - delta / K;
+    ss += e * e;
+  }
+  const double sigma2 = K > 1 ? ss / (K - 1) : NAN;
+  double prob;
+  if (sigma2 > 0.0) prob = 0.5 * std::erfc(-delta / std::sqrt(2.0 * K * sigma2));
+  else prob = delta == 0.0 ? 0.5 : (delta > 0.0 ? 1.0 : 0.0);
+  out->delta = delta;
+  out->sigma2 = sigma2;
+  out->prob_a_better = prob;
+  out->mcse = std::sqrt(var_mc);
+  if (out->delta_fold)
+    for (int k = 0; k < K; ++k) out->delta_fold[k] = ea[k] - eb[k];
   return PCV_OK;
 }
 

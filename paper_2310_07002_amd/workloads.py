@@ -364,13 +364,26 @@ def fold_subset(w: Workload, k0: int, k1: int) -> Workload:
     return sub
 
 
-def drop_covariates(w: Workload, cols) -> Workload:
+def drop_covariates(w: Workload, cols, zero: bool = False) -> Workload:
     """The same workload for the model without covariates `cols` (GLM
     families): the nested-model comparison of Section 2.3, model B missing
     covariates of model A.  Same folds, rows and random streams; the prior
     scales, mass-matrix entries and initial positions of the kept covariates
-    are those of the full model."""
+    are those of the full model.  zero=True keeps p and zeroes the columns
+    instead (the masked form of Appendix B: the dropped coefficients remain
+    as parameters the likelihood ignores), for paths built for fixed p."""
     assert w.family in (GAUSSIAN, LOGISTIC, POISSON), "GLM families only"
+    if zero:
+        sub = dataclasses.replace(w)
+        sub.name = w.name + "_zero_" + "_".join(str(int(c)) for c in np.atleast_1d(cols))
+        sub.X = w.X.copy()
+        sub.X[:, cols] = 0.0
+        if w.x_hi is not None:
+            sub.x_hi = w.x_hi.copy()
+            sub.x_lo = w.x_lo.copy()
+            sub.x_hi[:, cols] = 0
+            sub.x_lo[:, cols] = 0
+        return sub
     keep = np.setdiff1d(np.arange(w.p), np.asarray(cols))
     sub = dataclasses.replace(w)
     sub.name = w.name + "_minus_" + "_".join(str(int(c)) for c in np.atleast_1d(cols))

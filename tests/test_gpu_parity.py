@@ -482,3 +482,55 @@ def test_graph_replay_matches_eager(dev):
     ag, ae = g.get_accumulators(w.n_blocks), e.get_accumulators(w.n_blocks)
     for k in ("U", "U2", "Z", "blk_mean", "blk_m2", "n_accept"):
         np.testing.assert_array_equal(ag[k], ae[k])
+
+
+# ---------------------------------------------------------------- model comparison
+
+def test_model_comparison_replays_oracle(dev):
+    """LOO of the conjugate Gaussian: model A with all covariates, model B
+    without its strongest one, both full runs; pcv_compare against the
+    oracle's comparison of its own runs."""
+    a = W.make("c1")
+    b = W.drop_covariates(a, [int(np.argmax(np.abs(a.truth)))])
+    _say("[compare] c1 fp64, full runs of both models")
+    ra, rb = sampler.run_all(a), sampler.run_all(b)
+    da = diagnostics.from_accumulators(ra.acc, a.K, a.L, a.batch_size)
+    db = diagnostics.from_accumulators(rb.acc, b.K, b.L, b.batch_size)
+    want = diagnostics.compare(da["elpd_fold"], da["mcse_fold"], db["elpd_fold"], db["mcse_fold"])
+    sa, sb = binding.PCV.from_workload(a), binding.PCV.from_workload(b)
+    sa.step(a.n_iter)
+    sb.step(b.n_iter)
+    got = sa.compare(sb)
+    _say(f"    delta {got['delta']:.4f} (oracle {want['delta']:.4f}) mcse {got['mcse']:.4f} "
+         f"Pr(A>B) {got['prob_a_better']:.6f}")
+    assert got["delta"] == pytest.approx(want["delta"], rel=1e-9)
+    assert got["sigma2"] == pytest.approx(want["sigma2"], rel=1e-8)
+    assert got["prob_a_better"] == pytest.approx(want["prob_a_better"], abs=1e-9)
+    assert got["mcse"] == pytest.approx(want["mcse"], rel=1e-7)
+    np.testing.assert_allclose(got["delta_fold"], want["delta_fold"], rtol=1e-9, atol=1e-12)
+    swapped = sb.compare(sa)
+    assert swapped["delta"] == -got["delta"] and swapped["prob_a_better"] == pytest.approx(1 - got["prob_a_better"])
+
+
+def test_model_comparison_on_matrix_cores(dev):
+    """Nested logistic models on the bf16x3 path (model B: two columns
+    zeroed); the comparison equals the oracle's formulas applied to the two
+    runs' fold estimates, and runs on different folds are refused."""
+    a = W.fold_subset(W.make("c5"), 0, 64)
+    a = dataclasses.replace(a, n_warmup=20, batch_size=10)
+    b = W.drop_covariates(a, [3, 77], zero=True)
+    sa = binding.PCV.from_workload(a, precision=W.PREC_BF16X3)
+    sb = binding.PCV.from_workload(b, precision=W.PREC_BF16X3, x_planes=True)
+    sa.step(80)
+    sb.step(80)
+    ea, eb = sa.elpd(), sb.elpd()
+    want = diagnostics.compare(ea["elpd_fold"], ea["mcse_fold"], eb["elpd_fold"], eb["mcse_fold"])
+    got = sa.compare(sb)
+    assert got["delta"] == pytest.approx(want["delta"], rel=1e-12, abs=1e-12)
+    assert got["sigma2"] == pytest.approx(want["sigma2"], rel=1e-12)
+    assert got["prob_a_better"] == pytest.approx(want["prob_a_better"], abs=1e-12)
+    assert got["mcse"] == pytest.approx(want["mcse"], rel=1e-12)
+    other = binding.PCV.from_workload(W.fold_subset(W.make("c5"), 64, 128), precision=W.PREC_BF16X3)
+    other.step(25)
+    with pytest.raises(binding.PcvError, match="same folds"):
+        sa.compare(other)
