@@ -34,6 +34,7 @@ import numpy as np
 TAG_MOMENTUM = 1
 TAG_ACCEPT = 2
 TAG_SHUFFLE = 3
+TAG_PREDICT = 4      # predictive draws of the test rows (DSS)
 
 _M0 = np.uint64(0xD2511F53)
 _M1 = np.uint64(0xCD9E8D57)
@@ -119,3 +120,12 @@ def shuffle_indices(seed: int, fold: int, replicate: int, L: int, D: int) -> np.
     u = uniform_from_words(w0, w1)
     idx = np.minimum(np.floor(u * L).astype(np.int64), L - 1)
     return idx.reshape(L, D)
+
+
+def predictive_words(seed: int, chains, t: int, v: int):
+    """Philox words for the predictive draws of iteration t: one block per
+    (chain, test-row slot j), counter (chain, t, TAG_PREDICT, j).  Returns four
+    [len(chains), v] uint64 arrays."""
+    chains = np.asarray(chains, dtype=np.uint64)
+    jj = np.arange(v, dtype=np.uint64)[None, :]
+    return philox4x32_10((chains[:, None], np.uint64(t), np.uint64(TAG_PREDICT), jj), seed_key(seed))

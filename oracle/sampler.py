@@ -39,7 +39,7 @@ from typing import Optional
 
 import numpy as np
 
-from . import folds, hmc
+from . import folds, hmc, scores
 
 
 RHAT_WELFORD, RHAT_SHIFTED_SUMS = 0, 1
@@ -118,6 +118,8 @@ class Run:
     state: hmc.ChainState
     acc: Accumulators
     t: int                              # next global iteration
+    score_acc: Optional[scores.ScoreAccumulators] = None   # HS / DSS sums (workload flag `scores`)
+    score_rows: Optional[np.ndarray] = None                # [C, vmax] test rows per chain
     draws: Optional[np.ndarray] = None  # [C, N] stored s (when requested)
     accepted: Optional[np.ndarray] = None   # [C, iters] accept decisions (when requested)
 
@@ -129,7 +131,12 @@ def start(w) -> Run:
     acc = Accumulators.empty(w.C, w.n_blocks, getattr(w, "rhat_mode", RHAT_WELFORD))
     if w.n_warmup == 0:
         fix_center(acc, w.L)
-    return Run(state=st, acc=acc, t=0)
+    run = Run(state=st, acc=acc, t=0)
+    flags = getattr(w, "scores", 0)
+    if flags:
+        run.score_rows = scores.rows_of_chains(roles, w.L)
+        run.score_acc = scores.ScoreAccumulators(w.C, run.score_rows.shape[1], flags)
+    return run
 
 
 def advance(w, run: Run, n_iter: int, store_draws: bool = False,
@@ -152,6 +159,10 @@ def advance(w, run: Run, n_iter: int, store_draws: bool = False,
                 fix_center(run.acc, w.L)
         else:
             accumulate(run.acc, run.state.s, t - w.n_warmup, b, G, D)
+            if run.score_acc is not None:
+                r = run.score_rows
+                yt = np.where(r >= 0, w.y[np.maximum(r, 0)], np.nan)
+                scores.accumulate(w, run.score_acc, scores.test_eta(w, run.state.q, r), yt, t)
             run.acc.n_accept += accepted
             run.acc.n_divergent += divergent
             if store_draws:
