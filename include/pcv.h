@@ -91,6 +91,13 @@ enum {
                             fp64 (a stored split such as the synthetic c4/c5 designs) */
 };
 
+/* Extra scoring rules accumulated online (bit mask; Appendix, HS and DSS). */
+enum {
+  PCV_SCORE_HS = 1,    /* Hyvarinen score (continuous responses: Gaussian family)    */
+  PCV_SCORE_DSS = 2    /* Dawid-Sebastiani score, from one predictive draw per chain,
+                          transition and test row                                      */
+};
+
 /* How Rhat is accumulated (Section 4.2). */
 enum {
   PCV_RHAT_WELFORD = 0,       /* per-block Welford mean and M2, Chan-merged           */
@@ -122,6 +129,7 @@ typedef struct pcv_model {
   int64_t chain_offset;        /* global id of chain 0 (0 for a full run)            */
   int32_t x_format;            /* PCV_X_*: encoding of the X argument of pcv_init   */
   int32_t rhat_mode;           /* PCV_RHAT_*                                         */
+  int32_t scores;              /* PCV_SCORE_* mask (0 = LogS only)                   */
 } pcv_model;
 
 typedef struct pcv_diag {
@@ -191,6 +199,20 @@ pcv_status pcv_elpd(pcv_ctx ctx, double* elpd, double* mcse, double* elpd_fold, 
  * Synchronises.  PCV_ERR_STATE before 2 draws, PCV_ERR_INVALID_ARG if R < 1. */
 pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* rhat_max_rep,
                                  double* rhat_rep);
+
+/* Hyvarinen (HS) and Dawid-Sebastiani (DSS) cross-validation scores
+ * (Appendix, sections HS and DSS; positively oriented), summed over folds
+ * and per fold (K entries each; any output may be NULL).  Per fold k with
+ * test rows V_k, from the post-warm-up draws of its L chains:
+ * - HS_k = sum_i (-2 mu1_i + mu2_i^2), mu1_i the average of
+ *   d2 log p/dy_i^2 + (d log p/dy_i)^2 and mu2_i that of d log p/dy_i;
+ * - DSS_k = -log|Sigma| - (y - mu)' Sigma^-1 (y - mu), mu and Sigma the mean
+ *   and covariance of the predictive draws of y_{V_k}.
+ * DSS_k is NaN if Sigma is not positive definite.  The scores must be
+ * enabled in pcv_model.scores.  Synchronises.
+ * Errors: PCV_ERR_INVALID_ARG if a requested score is not enabled;
+ * PCV_ERR_STATE before 2 post-warm-up draws. */
+pcv_status pcv_scores(pcv_ctx ctx, double* hs, double* hs_fold, double* dss, double* dss_fold);
 
 /* Pairwise model comparison from two runs on the same folds (same fold
  * encoding and arrays, checked by fingerprint): context a holds model A,

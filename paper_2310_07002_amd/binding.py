@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "PCV_OK", 1: "PCV_ERR_INVALID_ARG", 2: "PCV_ERR_NOMEM", 3: "P
                 4: "PCV_ERR_STATE", 5: "PCV_ERR_UNSUPPORTED"}
 
 EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_elpd",
-            "pcv_shuffle_benchmark", "pcv_compare", "pcv_destroy", "pcv_last_error", "pcv_status_str",
+            "pcv_shuffle_benchmark", "pcv_scores", "pcv_compare", "pcv_destroy", "pcv_last_error", "pcv_status_str",
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
             "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
             "pcv_timing_enable", "pcv_timing_read"]
@@ -53,10 +53,12 @@ class pcv_model(ctypes.Structure):
                 ("n_warmup", ctypes.c_int64), ("batch_size", ctypes.c_int32),
                 ("batches_per_block", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64),
-                ("x_format", ctypes.c_int32), ("rhat_mode", ctypes.c_int32)]
+                ("x_format", ctypes.c_int32), ("rhat_mode", ctypes.c_int32),
+                ("scores", ctypes.c_int32)]
 
 X_FP64, X_BF16_HILO = 0, 1
 RHAT_WELFORD, RHAT_SHIFTED_SUMS = 0, 1
+SCORE_HS, SCORE_DSS = 1, 2
 
 
 class pcv_comparison(ctypes.Structure):
@@ -97,6 +99,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_elpd": ([P, dp, dp, dp, dp], I32),
         "pcv_shuffle_benchmark": ([P, I32, U64, dp, dp], I32),
         "pcv_compare": ([P, P, ctypes.POINTER(pcv_comparison)], I32),
+        "pcv_scores": ([P, dp, dp, dp, dp], I32),
         "pcv_destroy": ([P], None),
         "pcv_last_error": ([P], ctypes.c_char_p),
         "pcv_status_str": ([I32], ctypes.c_char_p),
@@ -152,7 +155,7 @@ class PCV:
                  n_groups: int = 0, sigma: float = 1.0, prior_scale=None, step_size: float,
                  n_leapfrog: int, inv_mass, init_pos, n_warmup: int, batch_size: int,
                  batches_per_block: int, n_blocks: int, seed: int, chain_offset: int = 0,
-                 x_format: int = X_FP64, rhat_mode: int = RHAT_WELFORD, stream=None):
+                 x_format: int = X_FP64, rhat_mode: int = RHAT_WELFORD, scores: int = 0, stream=None):
         """X: [n, p] float64, or with x_format=X_BF16_HILO a [2, n, p] uint16
         array of bf16 bit patterns (hi plane, lo plane)."""
         self._lib = load_library()
@@ -166,6 +169,7 @@ class PCV:
         y = np.ascontiguousarray(y, dtype=np.float64)
         self.n, self.p, self.K, self.L = n, p, int(K), int(L)
         self.C = self.K * self.L
+        self._scores = int(scores)
         self.d = p + 2 + n_groups if group_of is not None else p
         keep = []
 
@@ -196,7 +200,7 @@ class PCV:
         m.n_warmup, m.batch_size = n_warmup, batch_size
         m.batches_per_block, m.n_blocks = batches_per_block, n_blocks
         m.seed, m.chain_offset = seed, chain_offset
-        m.x_format, m.rhat_mode = x_format, rhat_mode
+        m.x_format, m.rhat_mode, m.scores = x_format, rhat_mode, scores
         f = pcv_folds()
         f.kind = fold_kind
         f.fold_index = fi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if fi is not None else None
@@ -220,7 +224,8 @@ class PCV:
         if rhat_mode is None:
             rhat_mode = getattr(w, "rhat_mode", RHAT_WELFORD)
         return cls(family=w.family, precision=w.precision if precision is None else precision,
-                   X=X, x_format=xf, rhat_mode=rhat_mode, y=w.y, K=w.K, L=w.L, fold_kind=w.fold_kind,
+                   X=X, x_format=xf, rhat_mode=rhat_mode, scores=getattr(w, "scores", 0), y=w.y,
+                   K=w.K, L=w.L, fold_kind=w.fold_kind,
                    fold_index=w.fold_index,
                    intervals=w.intervals, roles=w.roles, group_of=w.group_of, n_groups=w.n_groups,
                    sigma=w.sigma, prior_scale=w.prior_scale, step_size=w.step_size,
@@ -325,6 +330,22 @@ class PCV:
             i64(out["n_divergent"])), "pcv_get_accumulators")
         out["blk_mean"] = out["blk_mean"].reshape(n_blocks, C).T.copy()
         out["blk_m2"] = out["blk_m2"].reshape(n_blocks, C).T.copy()
+        return out
+
+    def scores(self) -> dict:
+        """HS and/or DSS (those enabled in the model), total and per fold."""
+        out = {}
+        hs, dss = ctypes.c_double(), ctypes.c_double()
+        hf, df = np.zeros(self.K), np.zeros(self.K)
+        want_h, want_d = bool(self._scores & SCORE_HS), bool(self._scores & SCORE_DSS)
+        self._check(self._lib.pcv_scores(self._ctx, ctypes.byref(hs) if want_h else None,
+                                         _dptr(hf) if want_h else None,
+                                         ctypes.byref(dss) if want_d else None,
+                                         _dptr(df) if want_d else None), "pcv_scores")
+        if want_h:
+            out.update(hs=hs.value, hs_fold=hf)
+        if want_d:
+            out.update(dss=dss.value, dss_fold=df)
         return out
 
     def compare(self, other: "PCV") -> dict:

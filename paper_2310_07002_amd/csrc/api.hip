@@ -96,6 +96,8 @@ struct pcv_ctx_s {
   uint64_t fold_fp = 0;       // of the fold set alone (model comparison)
   std::vector<int32_t> group_of_host;   // HIER: groups (VALU partitions when autotuning)
   int split_cap = 0;                    // MFMA: row splits the partial buffers hold
+  std::vector<int32_t> test_ptr_host;   // [K+1] test rows of each fold (CSR)
+  std::vector<int64_t> sq_ptr_host;     // [K+1] prefix sums of squared test-set sizes
 };
 
 namespace {
@@ -369,6 +371,10 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown x_format");
   if (md->rhat_mode != PCV_RHAT_WELFORD && md->rhat_mode != PCV_RHAT_SHIFTED_SUMS)
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown rhat_mode");
+  if (md->scores < 0 || md->scores > (PCV_SCORE_HS | PCV_SCORE_DSS))
+    return fail(ctx, PCV_ERR_INVALID_ARG, "unknown scores");
+  if ((md->scores & PCV_SCORE_HS) && md->family != PCV_FAMILY_GAUSSIAN)
+    return fail(ctx, PCV_ERR_UNSUPPORTED, "the Hyvarinen score needs a continuous response (Gaussian family)");
   if (!(md->step_size > 0) || !std::isfinite(md->step_size)) return fail(ctx, PCV_ERR_INVALID_ARG, "step_size must be > 0");
   if (md->n_leapfrog < 1) return fail(ctx, PCV_ERR_INVALID_ARG, "n_leapfrog must be >= 1");
   if (md->batch_size < 1 || md->batches_per_block < 1 || md->n_blocks < 1 || md->n_blocks > MAX_BLOCKS)
@@ -556,6 +562,30 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   TRY(upload(ctx, &tr, test_rows.data(), test_rows.size()));
   m.test_ptr = tp;
   m.test_rows = tr;
+  m.scores = md->scores;
+  ctx->test_ptr_host = test_ptr;
+  if (md->scores) {
+    const size_t nnz = static_cast<size_t>(test_ptr[K]);
+    std::vector<int64_t> sq(K + 1, 0);
+    for (int k = 0; k < K; ++k) {
+      const int64_t v = test_ptr[k + 1] - test_ptr[k];
+      sq[k + 1] = sq[k] + v * v;
+    }
+    ctx->sq_ptr_host = sq;
+    const size_t Lz = static_cast<size_t>(md->L);
+    if (md->scores & PCV_SCORE_HS) {
+      TRY(dalloc(ctx, &m.hs1, static_cast<size_t>(C)));
+      TRY(dalloc(ctx, &m.hs2, Lz * nnz));
+    }
+    if (md->scores & PCV_SCORE_DSS) {
+      TRY(dalloc(ctx, &m.dx, Lz * nnz));
+      TRY(dalloc(ctx, &m.rcur, Lz * nnz));
+      TRY(dalloc(ctx, &m.dxx, Lz * static_cast<size_t>(sq[K])));
+      int64_t* sqd;
+      TRY(upload(ctx, &sqd, sq.data(), sq.size()));
+      m.sq_ptr = sqd;
+    }
+  }
   if (fm->kind == PCV_FOLDS_INDEX) {
     int32_t* fi;
     TRY(upload(ctx, &fi, fm->fold_index, n));
@@ -701,6 +731,10 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   CK(launch_fill(m.bm2, 0.0, static_cast<int64_t>(m.D) * C, ctx->st));
   CK(launch_fill(m.wsum, 0.0, C, ctx->st));
   CK(launch_fill(m.center, 0.0, K, ctx->st));
+  if (m.hs1) CK(launch_fill(m.hs1, 0.0, C, ctx->st));
+  if (m.hs2) CK(launch_fill(m.hs2, 0.0, static_cast<int64_t>(m.L) * ctx->test_ptr_host[K], ctx->st));
+  if (m.dx) CK(launch_fill(m.dx, 0.0, static_cast<int64_t>(m.L) * ctx->test_ptr_host[K], ctx->st));
+  if (m.dxx) CK(launch_fill(m.dxx, 0.0, static_cast<int64_t>(m.L) * ctx->sq_ptr_host[K], ctx->st));
   CK(hipMemsetAsync(m.nacc, 0, sizeof(int64_t) * C, ctx->st));
   CK(hipMemsetAsync(m.ndiv, 0, sizeof(int64_t) * C, ctx->st));
   CK(hipStreamSynchronize(ctx->st));
@@ -994,7 +1028,7 @@ struct CkptHeader {
   uint32_t version;
   int32_t family, precision, fold_kind;
   int64_t n, p, d, C;
-  int32_t K, L, D, b, Gb, S, rhat_mode, reserved;
+  int32_t K, L, D, b, Gb, S, rhat_mode, scores;
   uint64_t seed;
   int64_t chain_offset, n_warmup;
   double eps;
@@ -1025,6 +1059,7 @@ CkptHeader ckpt_header_of(pcv_ctx ctx) {
   h.Gb = m.Gb;
   h.S = m.S;
   h.rhat_mode = m.rhat_mode;
+  h.scores = m.scores;
   h.seed = (static_cast<uint64_t>(m.key1) << 32) | m.key0;
   h.chain_offset = m.chain_offset;
   h.n_warmup = m.n_warmup;
@@ -1043,9 +1078,16 @@ std::vector<CkptArray> ckpt_arrays(pcv_ctx ctx) {
   const DevModel& m = ctx->m;
   const size_t C = m.C, dC = static_cast<size_t>(m.d) * m.C, DC = static_cast<size_t>(m.D) * m.C;
   const size_t K = static_cast<size_t>(m.K);
-  return {{m.q0, 8 * dC},  {m.g0, 8 * dC},   {m.logp0, 8 * C}, {m.s0, 8 * C},  {m.Z, 8 * C},
-          {m.U, 8 * C},    {m.U2, 8 * C},    {m.V, 8 * C},     {m.V2, 8 * C},  {m.bmean, 8 * DC},
-          {m.bm2, 8 * DC}, {m.nacc, 8 * C},  {m.ndiv, 8 * C},  {m.wsum, 8 * C}, {m.center, 8 * K}};
+  std::vector<CkptArray> a = {{m.q0, 8 * dC},  {m.g0, 8 * dC},  {m.logp0, 8 * C}, {m.s0, 8 * C},
+                              {m.Z, 8 * C},    {m.U, 8 * C},    {m.U2, 8 * C},    {m.V, 8 * C},
+                              {m.V2, 8 * C},   {m.bmean, 8 * DC}, {m.bm2, 8 * DC}, {m.nacc, 8 * C},
+                              {m.ndiv, 8 * C}, {m.wsum, 8 * C}, {m.center, 8 * K}};
+  const size_t Lnnz = static_cast<size_t>(m.L) * ctx->test_ptr_host[m.K];
+  if (m.hs1) a.push_back({m.hs1, 8 * C});
+  if (m.hs2) a.push_back({m.hs2, 8 * Lnnz});
+  if (m.dx) a.push_back({m.dx, 8 * Lnnz});
+  if (m.dxx) a.push_back({m.dxx, 8 * static_cast<size_t>(m.L) * ctx->sq_ptr_host[m.K]});
+  return a;
 }
 
 }  // namespace
@@ -1119,6 +1161,102 @@ pcv_status pcv_load(pcv_ctx ctx, const char* path) {
     off += a.bytes;
   }
   ctx->t = h.t;
+  return PCV_OK;
+}
+
+// ---- Hyvaerinen and Dawid-Sebastiani scores ---------------------------------
+
+namespace {
+
+// log|S| and m' S^-1 m by Cholesky (S symmetric, n x n, overwritten); false if
+// S is not positive definite.
+bool chol_logdet_quad(std::vector<double>& S, int n, std::vector<double> m, double* logdet, double* quad) {
+  for (int j = 0; j < n; ++j) {
+    double d = S[static_cast<size_t>(j) * n + j];
+    for (int k = 0; k < j; ++k) d -= S[static_cast<size_t>(j) * n + k] * S[static_cast<size_t>(j) * n + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    S[static_cast<size_t>(j) * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double e = S[static_cast<size_t>(i) * n + j];
+      for (int k = 0; k < j; ++k) e -= S[static_cast<size_t>(i) * n + k] * S[static_cast<size_t>(j) * n + k];
+      S[static_cast<size_t>(i) * n + j] = e / d;
+    }
+  }
+  double ld = 0.0, q = 0.0;
+  for (int i = 0; i < n; ++i) {   // forward solve L z = m, q = |z|^2
+    double e = m[i];
+    for (int k = 0; k < i; ++k) e -= S[static_cast<size_t>(i) * n + k] * m[k];
+    m[i] = e / S[static_cast<size_t>(i) * n + i];
+    q += m[i] * m[i];
+    ld += 2.0 * std::log(S[static_cast<size_t>(i) * n + i]);
+  }
+  *logdet = ld;
+  *quad = q;
+  return true;
+}
+
+}  // namespace
+
+pcv_status pcv_scores(pcv_ctx ctx, double* hs, double* hs_fold, double* dss, double* dss_fold) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  const DevModel& m = ctx->m;
+  if (((hs || hs_fold) && !(m.scores & PCV_SCORE_HS)) || ((dss || dss_fold) && !(m.scores & PCV_SCORE_DSS)))
+    return fail(ctx, PCV_ERR_INVALID_ARG, "a requested score was not enabled in pcv_model.scores");
+  const int64_t N = std::max<int64_t>(0, ctx->t - m.n_warmup);
+  const int K = m.K, L = m.L;
+  const double LN = static_cast<double>(L) * N;
+  if (N < 2) return fail(ctx, PCV_ERR_STATE, "scores need at least 2 post-warm-up draws");
+  CK(hipStreamSynchronize(ctx->st));
+  const std::vector<int32_t>& tp = ctx->test_ptr_host;
+  const size_t Lnnz = static_cast<size_t>(L) * tp[K];
+  if (m.scores & PCV_SCORE_HS) {
+    std::vector<double> h1(m.C), h2(Lnnz);
+    CK(hipMemcpy(h1.data(), m.hs1, 8 * h1.size(), hipMemcpyDeviceToHost));
+    CK(hipMemcpy(h2.data(), m.hs2, 8 * h2.size(), hipMemcpyDeviceToHost));
+    double tot = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const int v = tp[k + 1] - tp[k];
+      double s1 = 0.0, sq = 0.0;
+      for (int l = 0; l < L; ++l) s1 += h1[static_cast<size_t>(k) * L + l];
+      for (int a = 0; a < v; ++a) {
+        double s2 = 0.0;
+        for (int l = 0; l < L; ++l) s2 += h2[static_cast<size_t>(L) * tp[k] + static_cast<size_t>(l) * v + a];
+        const double mu2 = s2 / LN;
+        sq += mu2 * mu2;
+      }
+      const double hk = -2.0 * s1 / LN + sq;
+      if (hs_fold) hs_fold[k] = hk;
+      tot += hk;
+    }
+    if (hs) *hs = tot;
+  }
+  if (m.scores & PCV_SCORE_DSS) {
+    const std::vector<int64_t>& sp = ctx->sq_ptr_host;
+    std::vector<double> x(Lnnz), xx(static_cast<size_t>(L) * sp[K]);
+    CK(hipMemcpy(x.data(), m.dx, 8 * x.size(), hipMemcpyDeviceToHost));
+    CK(hipMemcpy(xx.data(), m.dxx, 8 * xx.size(), hipMemcpyDeviceToHost));
+    double tot = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const int v = tp[k + 1] - tp[k];
+      std::vector<double> sx(v, 0.0), S(static_cast<size_t>(v) * v, 0.0);
+      for (int l = 0; l < L; ++l) {
+        for (int a = 0; a < v; ++a) sx[a] += x[static_cast<size_t>(L) * tp[k] + static_cast<size_t>(l) * v + a];
+        const size_t o2 = static_cast<size_t>(L) * sp[k] + static_cast<size_t>(l) * v * v;
+        for (size_t ab = 0; ab < static_cast<size_t>(v) * v; ++ab) S[ab] += xx[o2 + ab];
+      }
+      std::vector<double> mv(v);
+      for (int a = 0; a < v; ++a) mv[a] = sx[a] / LN;
+      for (int a = 0; a < v; ++a)
+        for (int b = 0; b < v; ++b)
+          S[static_cast<size_t>(a) * v + b] = (S[static_cast<size_t>(a) * v + b] - sx[a] * sx[b] / LN) / (LN - 1.0);
+      double ld = 0.0, q = 0.0;
+      const double dk = chol_logdet_quad(S, v, mv, &ld, &q) ? -ld - q : NAN;
+      if (dss_fold) dss_fold[k] = dk;
+      tot += dk;
+    }
+    if (dss) *dss = tot;
+  }
   return PCV_OK;
 }
 

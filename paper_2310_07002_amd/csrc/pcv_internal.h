@@ -15,6 +15,7 @@ namespace pcv {
 constexpr uint32_t TAG_MOMENTUM = 1;
 constexpr uint32_t TAG_ACCEPT = 2;
 constexpr uint32_t TAG_SHUFFLE = 3;
+constexpr uint32_t TAG_PREDICT = 4;   // predictive draws of the test rows (DSS)
 constexpr double DIVERGENCE_THRESHOLD = 1000.0;
 constexpr int MAX_BLOCKS = 64;
 
@@ -57,6 +58,16 @@ struct DevModel {
   int rhat_mode;
   double* wsum;     // [C] sum of warm-up draws of s (shifted sums)
   double* center;   // [K] C_k, the fold's warm-up mean of s (shifted sums)
+  // Hyvaerinen / Dawid-Sebastiani scores (bit mask: 1 HS, 2 DSS).  Per chain
+  // c = k L + l, test-row slot a of its fold: [L * test_ptr[k] + l v_k + a];
+  // per row pair (a, b): [L * sq_ptr[k] + l v_k^2 + a v_k + b].
+  int scores;
+  double* hs1;      // [C] sum over draws and test rows of d2 + d1^2
+  double* hs2;      // [L nnz] sum over draws of d1 per test row
+  double* dx;       // [L nnz] sum over draws of (ytil - y)
+  double* dxx;      // [L sum_k v_k^2] sum over draws of (ytil_a - y_a)(ytil_b - y_b)
+  double* rcur;     // [L nnz] this draw's ytil - y (scratch)
+  const int64_t* sq_ptr;  // [K+1]
   // device-side transition counter (read when a kernel is given t < 0, so
   // one captured graph of a transition can be replayed)
   int64_t* t_dev;
@@ -279,6 +290,62 @@ __device__ __forceinline__ void accumulate_draw(const DevModel& m, int64_t c, in
   }
 }
 
+// One predictive draw of y given eta from the Philox block w: Gaussian by
+// Box-Muller, Bernoulli by threshold, Poisson by inverse cdf.
+template <int FAM>
+__device__ double predictive_draw(const DevModel& m, double eta, W4 w) {
+  const double u = uniform01(w.x, w.y);
+  if (FAM == FAM_GAUSS) {
+    const double u2 = uniform01(w.z, w.w);
+    return eta + m.sigma * sqrt(-2.0 * log(u)) * cos(2.0 * M_PI * u2);
+  }
+  if (FAM == FAM_LOGIT || FAM == FAM_HIER) return u < 1.0 / (1.0 + exp(-eta)) ? 1.0 : 0.0;
+  const double lam = exp(eta);
+  double p = exp(-lam), F = p, k = 0.0;
+  for (int j = 1; u > F && j <= 100000; ++j) {
+    p = p * lam / j;
+    F += p;
+    k += 1.0;
+  }
+  return k;
+}
+
+// HS and DSS sums of one post-warm-up draw at the accepted state q0.
+template <int FAM>
+__device__ void accumulate_scores(const DevModel& m, int64_t c, int64_t t) {
+  const int k = static_cast<int>(c / m.L);
+  const int64_t l = c - static_cast<int64_t>(k) * m.L;
+  const int beg = m.test_ptr[k], v = m.test_ptr[k + 1] - beg;
+  const int64_t o1 = static_cast<int64_t>(m.L) * beg + l * v;
+  const uint32_t gc = static_cast<uint32_t>(m.chain_offset + c);
+  double h1 = 0.0;
+  for (int a = 0; a < v; ++a) {
+    const int64_t i = m.test_rows[beg + a];
+    const double eta = eta_row64(m, m.q0, c, i);
+    const double y = m.y64[i];
+    if (m.scores & 1) {
+      const double d1 = -(y - eta) * m.inv_sigma2;
+      h1 += -m.inv_sigma2 + d1 * d1;
+      m.hs2[o1 + a] += d1;
+    }
+    if (m.scores & 2) {
+      const W4 w = philox4x32_10(W4{gc, static_cast<uint32_t>(t), TAG_PREDICT, static_cast<uint32_t>(a)}, m.key0,
+                                 m.key1);
+      const double r = predictive_draw<FAM>(m, eta, w) - y;
+      m.dx[o1 + a] += r;
+      m.rcur[o1 + a] = r;
+    }
+  }
+  if (m.scores & 1) m.hs1[c] += h1;
+  if (m.scores & 2) {
+    const int64_t o2 = static_cast<int64_t>(m.L) * m.sq_ptr[k] + l * v * v;
+    for (int a = 0; a < v; ++a) {
+      const double ra = m.rcur[o1 + a];
+      for (int b = 0; b < v; ++b) m.dxx[o2 + static_cast<int64_t>(a) * v + b] += ra * m.rcur[o1 + b];
+    }
+  }
+}
+
 // Metropolis test at the end of a trajectory (q1, pm, logp1, g1), state
 // selection, log predictive at the new state and accumulation.
 template <int FAM>
@@ -309,6 +376,7 @@ __device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
     if (m.rhat_mode == 1) m.wsum[c] += m.s0[c];
   } else {
     accumulate_draw(m, c, t - m.n_warmup, m.s0[c]);
+    if (m.scores) accumulate_scores<FAM>(m, c, t);
     m.nacc[c] += accepted ? 1 : 0;
     m.ndiv[c] += divergent ? 1 : 0;
   }

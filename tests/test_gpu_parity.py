@@ -534,3 +534,47 @@ def test_model_comparison_on_matrix_cores(dev):
     other.step(25)
     with pytest.raises(binding.PcvError, match="same folds"):
         sa.compare(other)
+
+
+# ---------------------------------------------------------------- HS and DSS
+
+def _score_replay(w, n_iter, prec):
+    from oracle import scores as sc
+    run = sampler.run_all(w, n_iter=n_iter)
+    sizes = [len(t) for t in sc.test_rows_of_folds(folds.roles_of(w))]
+    want = sc.fold_scores(run.score_acc, w.K, w.L, run.acc.n_draws, sizes)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    s.step(n_iter)
+    return want, s.scores()
+
+
+@pytest.mark.parametrize("name,folds_,prec", [("c1", (0, 40), "fp64"), ("c3", (0, 30), "fp64")])
+def test_hs_dss_replay_oracle_gaussian(dev, name, folds_, prec):
+    """Gaussian: HS and DSS per fold from the device's sums equal the oracle's
+    (one test row per fold for c1, five for the hv-block folds of c3)."""
+    w = dataclasses.replace(W.fold_subset(W.make(name), *folds_), n_warmup=30, scores=3)
+    want, got = _score_replay(w, 130, prec)
+    _say(f"[scores] {name}: HS {got['hs']:.4f} (oracle {want['hs']:.4f}) DSS {got['dss']:.4f} (oracle {want['dss']:.4f})")
+    np.testing.assert_allclose(got["hs_fold"], want["hs_fold"], rtol=1e-9)
+    np.testing.assert_allclose(got["dss_fold"], want["dss_fold"], rtol=1e-8, atol=1e-9)
+
+
+@pytest.mark.parametrize("base,v,L", [("c5", 10, 4), ("c4", 40, 8)])
+def test_dss_replay_oracle_discrete(dev, base, v, L):
+    """Bernoulli and Poisson predictive draws: a 2000-row design of the same
+    family, 20 blocked folds of v test rows, on the plain fp64 path (which
+    replays the oracle transition for transition)."""
+    w0 = W.make(base)
+    n, K = 2000, 20
+    fi = np.where(np.arange(n) < K * v, np.arange(n) // v, -1).astype(np.int32)
+    w = dataclasses.replace(w0, X=w0.X[:n], y=w0.y[:n], x_hi=None, x_lo=None, fold_index=fi, K=K, L=L,
+                            init_pos=w0.init_pos[:K * L], n_warmup=10, batch_size=5, scores=2)
+    want, got = _score_replay(w, 50, "fp64u")
+    _say(f"[scores] {base} family {w.family}: DSS {got['dss']:.4f} (oracle {want['dss']:.4f})")
+    np.testing.assert_allclose(got["dss_fold"], want["dss_fold"], rtol=1e-8, atol=1e-9)
+
+
+def test_hs_refused_for_discrete_response(dev):
+    w = dataclasses.replace(W.fold_subset(W.make("c5"), 0, 4), scores=1)
+    with pytest.raises(binding.PcvError):
+        binding.PCV.from_workload(w)
