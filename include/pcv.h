@@ -130,6 +130,8 @@ typedef struct pcv_model {
   int32_t x_format;            /* PCV_X_*: encoding of the X argument of pcv_init   */
   int32_t rhat_mode;           /* PCV_RHAT_*                                         */
   int32_t scores;              /* PCV_SCORE_* mask (0 = LogS only)                   */
+  int64_t store_draws;         /* keep the first store_draws post-warm-up draws of s
+                                  of every chain on the device (Algorithm 1); 0 = none */
 } pcv_model;
 
 typedef struct pcv_diag {
@@ -155,6 +157,19 @@ typedef struct pcv_comparison {
                              add (eq mc-var)                                          */
   double* delta_fold;     /* optional, K entries, caller-owned                        */
 } pcv_comparison;
+
+/* Diagnostics from stored draws (Algorithm 1), computed after the run. */
+typedef struct pcv_posthoc_diag {
+  double elpd, mcse, ess;   /* two-pass LogS estimate, its MC s.e. and ESS (Sec. 4.1)  */
+  double rhat_max;          /* max over folds of the paper's Rhat (eq rhat)            */
+  double split_rhat_max;    /* ... of split Rhat (chain halves as chains)              */
+  double rank_rhat_max;     /* ... of rank-normalised split Rhat, bulk and folded
+                               (Vehtari et al., 2021)                                   */
+  int64_t n_draws;          /* stored draws per chain used                              */
+  double* rhat_fold;        /* optional, K entries each, caller-owned                   */
+  double* split_rhat_fold;
+  double* rank_rhat_fold;
+} pcv_posthoc_diag;
 
 typedef struct pcv_ctx_s* pcv_ctx;
 
@@ -213,6 +228,16 @@ pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* 
  * Errors: PCV_ERR_INVALID_ARG if a requested score is not enabled;
  * PCV_ERR_STATE before 2 post-warm-up draws. */
 pcv_status pcv_scores(pcv_ctx ctx, double* hs, double* hs_fold, double* dss, double* dss_fold);
+
+/* Stored draws (Algorithm 1; pcv_model.store_draws > 0).  pcv_get_draws
+ * copies the first min(stored, n_max) post-warm-up draws of s of every chain
+ * to s (C rows of n_out entries, chain-major; caller-owned).  pcv_posthoc
+ * computes from them, after the run, the two-pass estimates and three Rhats
+ * per fold (optional per-fold arrays of K entries).  Both synchronise.
+ * Errors: PCV_ERR_INVALID_ARG if draws are not stored or a buffer is bad;
+ * PCV_ERR_STATE with fewer than 4 stored draws (pcv_posthoc). */
+pcv_status pcv_get_draws(pcv_ctx ctx, double* s, int64_t n_max, int64_t* n_out);
+pcv_status pcv_posthoc(pcv_ctx ctx, pcv_posthoc_diag* out);
 
 /* Pairwise model comparison from two runs on the same folds (same fold
  * encoding and arrays, checked by fingerprint): context a holds model A,

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "PCV_OK", 1: "PCV_ERR_INVALID_ARG", 2: "PCV_ERR_NOMEM", 3: "P
                 4: "PCV_ERR_STATE", 5: "PCV_ERR_UNSUPPORTED"}
 
 EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_elpd",
-            "pcv_shuffle_benchmark", "pcv_scores", "pcv_compare", "pcv_destroy", "pcv_last_error", "pcv_status_str",
+            "pcv_shuffle_benchmark", "pcv_scores", "pcv_get_draws", "pcv_posthoc", "pcv_compare",
+            "pcv_destroy", "pcv_last_error", "pcv_status_str",
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
             "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
             "pcv_timing_enable", "pcv_timing_read"]
@@ -54,7 +55,7 @@ class pcv_model(ctypes.Structure):
                 ("batches_per_block", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64),
                 ("x_format", ctypes.c_int32), ("rhat_mode", ctypes.c_int32),
-                ("scores", ctypes.c_int32)]
+                ("scores", ctypes.c_int32), ("store_draws", ctypes.c_int64)]
 
 X_FP64, X_BF16_HILO = 0, 1
 RHAT_WELFORD, RHAT_SHIFTED_SUMS = 0, 1
@@ -65,6 +66,15 @@ class pcv_comparison(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("sigma2", ctypes.c_double),
                 ("prob_a_better", ctypes.c_double), ("mcse", ctypes.c_double),
                 ("delta_fold", ctypes.POINTER(ctypes.c_double))]
+
+
+class pcv_posthoc_diag(ctypes.Structure):
+    _fields_ = [("elpd", ctypes.c_double), ("mcse", ctypes.c_double), ("ess", ctypes.c_double),
+                ("rhat_max", ctypes.c_double), ("split_rhat_max", ctypes.c_double),
+                ("rank_rhat_max", ctypes.c_double), ("n_draws", ctypes.c_int64),
+                ("rhat_fold", ctypes.POINTER(ctypes.c_double)),
+                ("split_rhat_fold", ctypes.POINTER(ctypes.c_double)),
+                ("rank_rhat_fold", ctypes.POINTER(ctypes.c_double))]
 
 
 class pcv_diag(ctypes.Structure):
@@ -100,6 +110,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_shuffle_benchmark": ([P, I32, U64, dp, dp], I32),
         "pcv_compare": ([P, P, ctypes.POINTER(pcv_comparison)], I32),
         "pcv_scores": ([P, dp, dp, dp, dp], I32),
+        "pcv_get_draws": ([P, dp, I64, ctypes.POINTER(I64)], I32),
+        "pcv_posthoc": ([P, ctypes.POINTER(pcv_posthoc_diag)], I32),
         "pcv_destroy": ([P], None),
         "pcv_last_error": ([P], ctypes.c_char_p),
         "pcv_status_str": ([I32], ctypes.c_char_p),
@@ -155,7 +167,8 @@ class PCV:
                  n_groups: int = 0, sigma: float = 1.0, prior_scale=None, step_size: float,
                  n_leapfrog: int, inv_mass, init_pos, n_warmup: int, batch_size: int,
                  batches_per_block: int, n_blocks: int, seed: int, chain_offset: int = 0,
-                 x_format: int = X_FP64, rhat_mode: int = RHAT_WELFORD, scores: int = 0, stream=None):
+                 x_format: int = X_FP64, rhat_mode: int = RHAT_WELFORD, scores: int = 0,
+                 store_draws: int = 0, stream=None):
         """X: [n, p] float64, or with x_format=X_BF16_HILO a [2, n, p] uint16
         array of bf16 bit patterns (hi plane, lo plane)."""
         self._lib = load_library()
@@ -201,6 +214,7 @@ class PCV:
         m.batches_per_block, m.n_blocks = batches_per_block, n_blocks
         m.seed, m.chain_offset = seed, chain_offset
         m.x_format, m.rhat_mode, m.scores = x_format, rhat_mode, scores
+        m.store_draws = store_draws
         f = pcv_folds()
         f.kind = fold_kind
         f.fold_index = fi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if fi is not None else None
@@ -224,7 +238,8 @@ class PCV:
         if rhat_mode is None:
             rhat_mode = getattr(w, "rhat_mode", RHAT_WELFORD)
         return cls(family=w.family, precision=w.precision if precision is None else precision,
-                   X=X, x_format=xf, rhat_mode=rhat_mode, scores=getattr(w, "scores", 0), y=w.y,
+                   X=X, x_format=xf, rhat_mode=rhat_mode, scores=getattr(w, "scores", 0),
+                   store_draws=getattr(w, "store_draws", 0), y=w.y,
                    K=w.K, L=w.L, fold_kind=w.fold_kind,
                    fold_index=w.fold_index,
                    intervals=w.intervals, roles=w.roles, group_of=w.group_of, n_groups=w.n_groups,
@@ -347,6 +362,25 @@ class PCV:
         if want_d:
             out.update(dss=dss.value, dss_fold=df)
         return out
+
+    def get_draws(self, n_max: int) -> np.ndarray:
+        """Stored post-warm-up draws of s, [C, n] (n <= n_max)."""
+        buf = np.zeros(self.C * int(n_max))
+        n = ctypes.c_int64()
+        self._check(self._lib.pcv_get_draws(self._ctx, _dptr(buf), int(n_max), ctypes.byref(n)), "pcv_get_draws")
+        return buf[: self.C * n.value].reshape(self.C, n.value)
+
+    def posthoc(self) -> dict:
+        """Two-pass estimates and R-hats (paper's, split, rank-normalised) from the stored draws."""
+        out = pcv_posthoc_diag()
+        f = {k: np.zeros(self.K) for k in ("rhat_fold", "split_rhat_fold", "rank_rhat_fold")}
+        for k, a in f.items():
+            setattr(out, k, _dptr(a))
+        self._check(self._lib.pcv_posthoc(self._ctx, ctypes.byref(out)), "pcv_posthoc")
+        res = {k: getattr(out, k) for k in ("elpd", "mcse", "ess", "rhat_max", "split_rhat_max",
+                                            "rank_rhat_max", "n_draws")}
+        res.update(f)
+        return res
 
     def compare(self, other: "PCV") -> dict:
         """This run as model A against `other` as model B on the same folds."""

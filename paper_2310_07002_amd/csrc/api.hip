@@ -373,6 +373,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown rhat_mode");
   if (md->scores < 0 || md->scores > (PCV_SCORE_HS | PCV_SCORE_DSS))
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown scores");
+  if (md->store_draws < 0) return fail(ctx, PCV_ERR_INVALID_ARG, "store_draws must be >= 0");
   if ((md->scores & PCV_SCORE_HS) && md->family != PCV_FAMILY_GAUSSIAN)
     return fail(ctx, PCV_ERR_UNSUPPORTED, "the Hyvarinen score needs a continuous response (Gaussian family)");
   if (!(md->step_size > 0) || !std::isfinite(md->step_size)) return fail(ctx, PCV_ERR_INVALID_ARG, "step_size must be > 0");
@@ -564,6 +565,10 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   m.test_rows = tr;
   m.scores = md->scores;
   ctx->test_ptr_host = test_ptr;
+  if (md->store_draws > 0) {
+    TRY(dalloc(ctx, &m.draws, static_cast<size_t>(md->store_draws) * static_cast<size_t>(C)));
+    m.draws_cap = md->store_draws;
+  }
   if (md->scores) {
     const size_t nnz = static_cast<size_t>(test_ptr[K]);
     std::vector<int64_t> sq(K + 1, 0);
@@ -1029,6 +1034,7 @@ struct CkptHeader {
   int32_t family, precision, fold_kind;
   int64_t n, p, d, C;
   int32_t K, L, D, b, Gb, S, rhat_mode, scores;
+  int64_t draws_cap;
   uint64_t seed;
   int64_t chain_offset, n_warmup;
   double eps;
@@ -1037,7 +1043,7 @@ struct CkptHeader {
   uint64_t payload_bytes;
   uint64_t payload_hash;
 };
-static_assert(sizeof(CkptHeader) == 152, "checkpoint header has no padding");
+static_assert(sizeof(CkptHeader) == 160, "checkpoint header has no padding");
 constexpr char kCkptMagic[8] = {'P', 'C', 'V', 'C', 'K', 'P', 'T', '1'};
 
 CkptHeader ckpt_header_of(pcv_ctx ctx) {
@@ -1060,6 +1066,7 @@ CkptHeader ckpt_header_of(pcv_ctx ctx) {
   h.S = m.S;
   h.rhat_mode = m.rhat_mode;
   h.scores = m.scores;
+  h.draws_cap = m.draws_cap;
   h.seed = (static_cast<uint64_t>(m.key1) << 32) | m.key0;
   h.chain_offset = m.chain_offset;
   h.n_warmup = m.n_warmup;
@@ -1087,6 +1094,7 @@ std::vector<CkptArray> ckpt_arrays(pcv_ctx ctx) {
   if (m.hs2) a.push_back({m.hs2, 8 * Lnnz});
   if (m.dx) a.push_back({m.dx, 8 * Lnnz});
   if (m.dxx) a.push_back({m.dxx, 8 * static_cast<size_t>(m.L) * ctx->sq_ptr_host[m.K]});
+  if (m.draws) a.push_back({m.draws, 8 * static_cast<size_t>(m.draws_cap) * C});
   return a;
 }
 
@@ -1257,6 +1265,59 @@ pcv_status pcv_scores(pcv_ctx ctx, double* hs, double* hs_fold, double* dss, dou
     }
     if (dss) *dss = tot;
   }
+  return PCV_OK;
+}
+
+// ---- stored draws (Algorithm 1) and post-hoc diagnostics ----------------------
+
+static int64_t stored_draws(pcv_ctx ctx) {
+  return std::min<int64_t>(std::max<int64_t>(0, ctx->t - ctx->m.n_warmup), ctx->m.draws_cap);
+}
+
+pcv_status pcv_get_draws(pcv_ctx ctx, double* s, int64_t n_max, int64_t* n_out) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!ctx->m.draws) return fail(ctx, PCV_ERR_INVALID_ARG, "draws are not stored (pcv_model.store_draws = 0)");
+  if (n_max < 0 || (n_max > 0 && !s)) return fail(ctx, PCV_ERR_INVALID_ARG, "bad output buffer");
+  const int64_t n = std::min(stored_draws(ctx), n_max), C = ctx->m.C;
+  CK(hipStreamSynchronize(ctx->st));
+  std::vector<double> buf(static_cast<size_t>(n) * C);
+  if (n > 0) CK(hipMemcpy(buf.data(), ctx->m.draws, 8 * buf.size(), hipMemcpyDeviceToHost));
+  for (int64_t c = 0; c < C; ++c)
+    for (int64_t i = 0; i < n; ++i) s[c * n + i] = buf[static_cast<size_t>(i) * C + c];
+  if (n_out) *n_out = n;
+  return PCV_OK;
+}
+
+pcv_status pcv_posthoc(pcv_ctx ctx, pcv_posthoc_diag* out) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!out) return fail(ctx, PCV_ERR_INVALID_ARG, "null output");
+  if (!ctx->m.draws) return fail(ctx, PCV_ERR_INVALID_ARG, "draws are not stored (pcv_model.store_draws = 0)");
+  const int64_t N = stored_draws(ctx), C = ctx->m.C;
+  const int K = ctx->m.K, L = ctx->m.L;
+  if (N < 4) return fail(ctx, PCV_ERR_STATE, "post-hoc diagnostics need at least 4 stored draws");
+  std::vector<double> s(static_cast<size_t>(N) * C);
+  int64_t got = 0;
+  TRY(pcv_get_draws(ctx, s.data(), N, &got));
+  double elpd = 0.0, var = 0.0, s2 = 0.0, sig2 = 0.0;
+  out->rhat_max = out->split_rhat_max = out->rank_rhat_max = -INFINITY;
+  for (int k = 0; k < K; ++k) {
+    PosthocFold f{};
+    posthoc_fold(s.data() + static_cast<size_t>(k) * L * N, L, N, ctx->m.b, f);
+    elpd += f.log_fhat;
+    var += f.sig2rel / (static_cast<double>(L) * N);
+    s2 += f.s2rel;
+    sig2 += f.sig2rel;
+    out->rhat_max = std::max(out->rhat_max, f.rhat);
+    out->split_rhat_max = std::max(out->split_rhat_max, f.split_rhat);
+    out->rank_rhat_max = std::max(out->rank_rhat_max, f.rank_rhat);
+    if (out->rhat_fold) out->rhat_fold[k] = f.rhat;
+    if (out->split_rhat_fold) out->split_rhat_fold[k] = f.split_rhat;
+    if (out->rank_rhat_fold) out->rank_rhat_fold[k] = f.rank_rhat;
+  }
+  out->elpd = elpd;
+  out->mcse = std::sqrt(var);
+  out->ess = static_cast<double>(L) * N * s2 / sig2;
+  out->n_draws = N;
   return PCV_OK;
 }
 

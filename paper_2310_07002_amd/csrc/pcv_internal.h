@@ -19,6 +19,14 @@ constexpr uint32_t TAG_PREDICT = 4;   // predictive draws of the test rows (DSS)
 constexpr double DIVERGENCE_THRESHOLD = 1000.0;
 constexpr int MAX_BLOCKS = 64;
 
+// Post-hoc statistics of one fold's stored draws s[l * N + i] (host code,
+// posthoc.hip): log fhat, pooled and batch-means variances of f = e^s relative
+// to fhat^2, and the paper's, split and rank-normalised split R-hats.
+struct PosthocFold {
+  double log_fhat, s2rel, sig2rel, rhat, split_rhat, rank_rhat;
+};
+void posthoc_fold(const double* s, int L, int64_t N, int b, PosthocFold& out);
+
 // ----------------------------------------------------------------------------
 // Kernel argument bundle (plain device pointers; passed by value).
 // ----------------------------------------------------------------------------
@@ -68,6 +76,9 @@ struct DevModel {
   double* dxx;      // [L sum_k v_k^2] sum over draws of (ytil_a - y_a)(ytil_b - y_b)
   double* rcur;     // [L nnz] this draw's ytil - y (scratch)
   const int64_t* sq_ptr;  // [K+1]
+  // stored post-warm-up draws of s (Algorithm 1): draw i of chain c at [i C + c]
+  double* draws;
+  int64_t draws_cap;
   // device-side transition counter (read when a kernel is given t < 0, so
   // one captured graph of a transition can be replayed)
   int64_t* t_dev;
@@ -377,6 +388,8 @@ __device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
   } else {
     accumulate_draw(m, c, t - m.n_warmup, m.s0[c]);
     if (m.scores) accumulate_scores<FAM>(m, c, t);
+    const int64_t di = t - m.n_warmup;
+    if (m.draws && di < m.draws_cap) m.draws[di * m.C + c] = m.s0[c];
     m.nacc[c] += accepted ? 1 : 0;
     m.ndiv[c] += divergent ? 1 : 0;
   }

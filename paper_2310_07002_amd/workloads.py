@@ -89,6 +89,7 @@ class Workload:
     chain_offset: int = 0                      # global id of chain 0
     rhat_mode: int = 0                         # 0 Welford blocks, 1 shifted sums (Algorithm A2)
     scores: int = 0                            # extra scores accumulated: 1 HS, 2 DSS (bit mask)
+    store_draws: int = 0                       # post-warm-up draws of s kept on the device (Algorithm 1)
     truth: Optional[np.ndarray] = None         # [d]
     x_hi: Optional[np.ndarray] = None          # [n, p] uint16 bf16 bits
     x_lo: Optional[np.ndarray] = None          # [n, p] uint16 bf16 bits

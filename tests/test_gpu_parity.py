@@ -578,3 +578,38 @@ def test_hs_refused_for_discrete_response(dev):
     w = dataclasses.replace(W.fold_subset(W.make("c5"), 0, 4), scores=1)
     with pytest.raises(binding.PcvError):
         binding.PCV.from_workload(w)
+
+
+# ---------------------------------------------------------------- stored draws (Algorithm 1)
+
+def test_stored_draws_and_posthoc_replay_oracle(dev):
+    from oracle import posthoc
+    w = dataclasses.replace(W.fold_subset(W.make("c1"), 0, 25), n_warmup=50, store_draws=300)
+    run = sampler.run_all(w, n_iter=50 + 320, store_draws=True)      # more draws than the capacity
+    s = binding.PCV.from_workload(w)
+    s.step(370)
+    d = s.get_draws(1000)
+    assert d.shape == (w.C, 300)
+    np.testing.assert_allclose(d, run.draws[:, :300], rtol=1e-10, atol=1e-12)
+    got = s.posthoc()
+    # rank statistics order near-ties differently when the values differ by
+    # rounding, so the post-hoc formulas are compared on the device's draws
+    want = posthoc.fold_rhats(d, w.K, w.L)
+    tp = diagnostics.two_pass(d, w.K, w.L, w.batch_size)
+    for k in ("rhat_fold", "split_rhat_fold", "rank_rhat_fold"):
+        np.testing.assert_allclose(got[k], want[k], rtol=1e-9, err_msg=k)
+    assert got["n_draws"] == 300
+    assert got["elpd"] == pytest.approx(tp["elpd"], rel=1e-12)
+    assert got["mcse"] == pytest.approx(tp["mcse"], rel=1e-9)
+    assert got["ess"] == pytest.approx(tp["ess"], rel=1e-9)
+
+
+def test_stored_draws_agree_with_online_on_matrix_cores(dev):
+    w = dataclasses.replace(W.fold_subset(W.make("c5"), 0, 64), n_warmup=20, batch_size=10, store_draws=200)
+    s = binding.PCV.from_workload(w, precision=W.PREC_BF16X3)
+    s.step(20 + 200)
+    on = s.diagnostics()
+    ph = s.posthoc()
+    np.testing.assert_allclose(ph["rhat_fold"], on["rhat_fold"], rtol=1e-9)
+    assert ph["elpd"] == pytest.approx(on["elpd"], rel=1e-12)
+    assert ph["split_rhat_max"] >= 1.0 - 1e-3 and np.isfinite(ph["rank_rhat_max"])
