@@ -20,7 +20,7 @@ Also reported on the same JSON line:
                 the same workload, a few steps, and the speedup over it
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5]
        [--precision bf16x3|bf16x5|fp64|fp32|fp64u] [--no-cpu-baseline]
-       [--no-plain-fp64] [--time-to-rhat] [--no-autotune]
+       [--no-plain-fp64] [--no-time-to-rhat] [--no-autotune]
 """
 from __future__ import annotations
 
@@ -111,7 +111,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-fp64", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--time-to-rhat", action="store_true")
+    ap.add_argument("--no-time-to-rhat", action="store_true",
+                    help="skip the second metric (wall time from init to R-hat_max < 1.01 at a batch end)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the analytic launch shape instead of timing candidates first")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -219,7 +220,7 @@ def main():
         except Exception as e:  # report, never hide
             line["plain_fp64"] = {"error": str(e)}
 
-    if args.time_to_rhat:
+    if not args.no_time_to_rhat:
         log("bench: full run for wall time to Rhat_max < 1.01")
         r = binding.PCV.from_workload(w, precision=PREC_NAMES[prec], stream=stream)
         if tune is not None:
@@ -249,6 +250,18 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle, bounded sample)")
         line["cpu_baseline"] = cpu_baseline(w)
+    # the same number of transitions at the other paths' measured rates
+    tr = line.get("time_to_rhat_max_1.01")
+    if tr and tr.get("draws") is not None and tr.get("reached", True):
+        n_tr = w.n_warmup + tr["draws"]
+        ext = {"transitions": n_tr}
+        pf = line.get("plain_fp64", {})
+        if "ms_per_step" in pf:
+            ext["plain_fp64_seconds"] = pf["ms_per_step"] * n_tr / 1e3
+        cb = line.get("cpu_baseline")
+        if cb:
+            ext["oracle_seconds"] = w.C * w.n_leapfrog * n_tr / cb["value"]
+        tr["extrapolated_same_transitions"] = ext
     print(json.dumps(line), flush=True)
 
 
