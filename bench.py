@@ -146,12 +146,13 @@ def main():
         ta = time.perf_counter()
         tune = s.autotune()
         tune["seconds"] = time.perf_counter() - ta
-        tune["knob"] = "row splits per chain tile" if prec.startswith("bf16") else "waves per workgroup"
+        kname = s.timing_read(reset=True)[2]
+        tune["knob"] = "waves per workgroup" if "fused" in kname else "row splits"
         log(f"bench: autotune chose {tune['knob']} = {tune['config']} ({tune['ms']:.4f} ms) in {tune['seconds']:.2f} s")
     s.step(args.warmup)
     torch.cuda.synchronize()
     s.timing_read(reset=True)
-    s.timing_enable(True)
+    s.timing_enable(True)           # HIP events around every hot-kernel launch (eager launches)
     log(f"bench: timing {args.steps} transitions")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -161,6 +162,14 @@ def main():
     s.timing_enable(False)
     k_ms, k_n, k_name = s.timing_read(reset=True)
     wall = t1 - t0
+    k_steps = args.steps
+    # the same transitions replayed as the captured graph (the production
+    # path of the split paths; the fused VALU path is one launch either way)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    g_wall = time.perf_counter() - g0
     grads = w.C * w.n_leapfrog * args.steps
     value = grads / wall
     ms_per_step = wall / args.steps * 1e3
@@ -171,7 +180,7 @@ def main():
     flops_per_launch = 4.0 * w.n * w.p * w.C
     if prec in ("fp64", "fp32"):
         # the fused transition kernel runs many transitions per launch
-        grads_per_launch = w.C * w.n_leapfrog * args.steps / max(k_n, 1)
+        grads_per_launch = w.C * w.n_leapfrog * k_steps / max(k_n, 1)
         flops_per_launch = 4.0 * w.n * w.p * grads_per_launch
     avg_s = k_ms / max(k_n, 1) / 1e3
     achieved = flops_per_launch / avg_s / 1e12 if avg_s > 0 else None
@@ -194,7 +203,9 @@ def main():
             "data": "synthetic (seeded; shaped like the paper's CV workloads, no datasets)",
             "config": {"workload": workload_label(w, prec), "folds": w.K, "chains_per_fold": w.L,
                        "chains": w.C, "leapfrog_steps": w.n_leapfrog, "parallelism": "single GPU"},
-            "roofline": roofline}
+            "roofline": roofline,
+            "graph_replay": {"ms_per_step": g_wall / args.steps * 1e3,
+                             "value": w.C * w.n_leapfrog * args.steps / g_wall}}
     if tune is not None:
         line["autotune"] = tune
 

@@ -16,6 +16,10 @@ namespace pcv {
 hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int mode, int64_t t0,
                        int n_iter, int n_steps, hipStream_t st);
 size_t valu_smem_bytes(bool fp64, int W, int family, int n_groups);
+hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int ns, double* Gpart,
+                            double* Vpart, bool value, hipStream_t st);
+hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, int ns, int mode, hipStream_t st);
+hipError_t launch_valu_sum(const DevModel& m, double* Gpart, int ns, hipStream_t st);
 int valu_pb(int64_t p, bool fp64);
 hipError_t launch_mfma(const DevModel& m, const uint4* Xpk, const float* ty, const int32_t* tfid, float* Gpart,
                        double* Vpart, int n_tiles, int tiles_per_split, int n_splits, int fwd, bool value,
@@ -49,7 +53,7 @@ hipError_t launch_tick(const DevModel& m, hipStream_t st);
 
 using namespace pcv;
 
-enum Path { PATH_VALU = 0, PATH_MFMA = 1, PATH_UNFUSED = 2 };
+enum Path { PATH_VALU = 0, PATH_MFMA = 1, PATH_UNFUSED = 2, PATH_VALU_SPLIT = 3 };
 
 struct pcv_ctx_s {
   DevModel m{};
@@ -102,8 +106,8 @@ struct pcv_ctx_s {
 
 namespace {
 
-const char* kGradKernelName[3] = {"k_valu (fused transition)", "k_mfma (bf16 split MFMA value+gradient)",
-                                  "rocblas_dgemm + k_unfused_resid (fp64 unfused)"};
+const char* kGradKernelName[4] = {"k_valu (fused transition)", "k_mfma (bf16 split MFMA value+gradient)",
+                                  "rocblas_dgemm + k_unfused_resid (fp64 unfused)", "k_valu_part (row-split VALU value+gradient)"};
 
 // Fingerprint of input arrays (FNV-1a over 8-byte words plus a shift to
 // spread high bits; not cryptographic): a checkpoint only resumes a run on
@@ -195,6 +199,14 @@ void timing_collect(pcv_ctx ctx) {
 // Partial gradient (and value) at q1 for the split paths.
 pcv_status split_partials(pcv_ctx ctx, bool value) {
   DevModel& m = ctx->m;
+  if (ctx->path == PATH_VALU_SPLIT) {
+    if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
+    timing_begin(ctx);
+    CK(launch_valu_part(m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, ctx->n_splits, ctx->Gpart64, ctx->Vpart, value,
+                        ctx->st));
+    timing_end(ctx);
+    return PCV_OK;
+  }
   if (ctx->path == PATH_MFMA) {
     if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
     timing_begin(ctx);
@@ -224,12 +236,24 @@ pcv_status split_partials(pcv_ctx ctx, bool value) {
 }
 
 pcv_status split_reduce(pcv_ctx ctx, int mode) {
-  if (ctx->path == PATH_MFMA) CK(launch_reduce_f32(ctx->m, ctx->Gpart, ctx->n_splits, mode, ctx->st));
+  if (ctx->path == PATH_VALU_SPLIT) {
+    // GLM: the split sums, prior and update per (coefficient, chain) thread;
+    // hierarchical: sum per (entry, chain) thread, then the chain rule per chain
+    if (ctx->m.family == FAM_HIER) {
+      CK(launch_valu_sum(ctx->m, ctx->Gpart64, ctx->n_splits, ctx->st));
+      CK(launch_valu_finish(ctx->m, ctx->Gpart64, 1, mode, ctx->st));
+    } else {
+      CK(launch_reduce_f64(ctx->m, ctx->Gpart64, ctx->n_splits, mode, ctx->st));
+    }
+  }
+  else if (ctx->path == PATH_MFMA) CK(launch_reduce_f32(ctx->m, ctx->Gpart, ctx->n_splits, mode, ctx->st));
   else CK(launch_reduce_f64(ctx->m, ctx->Gpart64, 1, mode, ctx->st));
   return PCV_OK;
 }
 
-int split_count(pcv_ctx ctx) { return ctx->path == PATH_MFMA ? ctx->n_splits : 1; }
+int split_count(pcv_ctx ctx) {
+  return ctx->path == PATH_MFMA || ctx->path == PATH_VALU_SPLIT ? ctx->n_splits : 1;
+}
 
 // Value and gradient at q1 into logp1 / g1 (no leapfrog update).
 pcv_status eval_q1(pcv_ctx ctx) {
@@ -301,23 +325,27 @@ pcv_status capture_transition(pcv_ctx ctx) {
 // Row ranges [wr[w], wr[w+1]) of the W waves of a fused-VALU workgroup.  For
 // the hierarchical family the cuts are moved to group starts so each group
 // has one owner wave.
-std::vector<int32_t> valu_partition(int64_t n, int W, const int32_t* group_of) {
+std::vector<int32_t> valu_partition_range(int64_t lo, int64_t hi, int W, const int32_t* group_of) {
   std::vector<int32_t> wr(W + 1);
-  for (int w = 0; w <= W; ++w) wr[w] = static_cast<int32_t>(n * w / W);
+  for (int w = 0; w <= W; ++w) wr[w] = static_cast<int32_t>(lo + (hi - lo) * w / W);
   if (group_of) {
     for (int w = 1; w < W; ++w) {
       int64_t i = std::max<int64_t>(wr[w], wr[w - 1]);
-      while (i > wr[w - 1] && i < n && group_of[i] == group_of[i - 1]) --i;
+      while (i > wr[w - 1] && i < hi && group_of[i] == group_of[i - 1]) --i;
       if (i <= wr[w - 1]) {
         i = std::max<int64_t>(wr[w], wr[w - 1]);
-        while (i < n && i > 0 && group_of[i] == group_of[i - 1]) ++i;
+        while (i < hi && i > lo && group_of[i] == group_of[i - 1]) ++i;
       }
-      wr[w] = static_cast<int32_t>(std::min<int64_t>(i, n));
+      wr[w] = static_cast<int32_t>(std::min<int64_t>(i, hi));
     }
     for (int w = 1; w <= W; ++w) wr[w] = std::max(wr[w], wr[w - 1]);
-    wr[W] = static_cast<int32_t>(n);
+    wr[W] = static_cast<int32_t>(hi);
   }
   return wr;
+}
+
+std::vector<int32_t> valu_partition(int64_t n, int W, const int32_t* group_of) {
+  return valu_partition_range(0, n, W, group_of);
 }
 
 bool finite_all(const double* a, int64_t n) {
@@ -490,6 +518,10 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     ctx->fp64 = md->precision == PCV_PREC_FP64;
     ctx->pb = valu_pb(p, ctx->fp64);
     if (!ctx->pb) return fail(ctx, PCV_ERR_UNSUPPORTED, "fused VALU path supports p <= 32 (fp64) or p <= 64 (fp32)");
+    // few chains and many rows: split rows across workgroups (partial sums
+    // reduced per leapfrog step) instead of one fused workgroup per 64 chains
+    const int64_t chain_blocks = (static_cast<int64_t>(md->K) * md->L + 63) / 64;
+    if (chain_blocks < 128 && n >= 2048) ctx->path = PATH_VALU_SPLIT;
   } else if (md->precision == PCV_PREC_BF16X3 || md->precision == PCV_PREC_BF16X5) {
     ctx->path = PATH_MFMA;
     ctx->fwd = md->precision == PCV_PREC_BF16X5 ? 5 : 3;
@@ -638,7 +670,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   TRY(dalloc(ctx, &ctx->Vpart, C));
 
   // ---- path-specific buffers -----------------------------------------------
-  if (ctx->path == PATH_VALU) {
+  if (ctx->path == PATH_VALU || ctx->path == PATH_VALU_SPLIT) {
     const int pb = ctx->pb;
     const int64_t npad = n;
     if (ctx->fp64) {
@@ -657,6 +689,33 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
       ctx->Xv = xd;
       m.X32 = xd;
     }
+    if (ctx->path == PATH_VALU_SPLIT) {
+      // W waves per workgroup, row splits so that (chain blocks x splits)
+      // fills the GPU several times over while each wave keeps >= 32 rows
+      int W = 4;
+      while (W > 1 && valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536) --W;
+      if (valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536)
+        return fail(ctx, PCV_ERR_UNSUPPORTED, "too many groups for the row-split path");
+      const int64_t chain_blocks = (C + 63) / 64;
+      const int64_t ns = std::max<int64_t>(1, std::min<int64_t>((2048 + chain_blocks - 1) / chain_blocks,
+                                                                n / (32 * W)));
+      ctx->W = W;
+      ctx->n_splits = static_cast<int>(ns);
+      if (hier) ctx->group_of_host.assign(md->group_of, md->group_of + n);
+      std::vector<int32_t> wr;
+      for (int64_t sp = 0; sp < ns; ++sp) {
+        const std::vector<int32_t> part =
+            valu_partition_range(n * sp / ns, n * (sp + 1) / ns, W, hier ? md->group_of : nullptr);
+        wr.insert(wr.end(), part.begin(), part.end());
+      }
+      TRY(upload(ctx, &ctx->wave_rows, wr.data(), wr.size()));
+      m.wave_rows = ctx->wave_rows;
+      const size_t R = static_cast<size_t>(p) + (hier ? static_cast<size_t>(md->n_groups) : 0);
+      TRY(dalloc(ctx, &ctx->Gpart64, static_cast<size_t>(ns) * R * C));
+      double* vp;
+      TRY(dalloc(ctx, &vp, static_cast<size_t>(ns) * C));
+      ctx->Vpart = vp;
+    } else {
     // waves per workgroup: enough rows per wave, LDS within 64 KB, and the
     // register budget of wide rows.
     int W = static_cast<int>(std::min<int64_t>(8, std::max<int64_t>(1, n / 64)));
@@ -670,6 +729,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     TRY(dalloc(ctx, &ctx->wave_rows, 9));   // room for any W <= 8 (autotuning)
     CK(hipMemcpy(ctx->wave_rows, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice));
     m.wave_rows = ctx->wave_rows;
+    }
   } else if (ctx->path == PATH_MFMA) {
     const int R = mfma_rows_per_tile();
     ctx->n_tiles = static_cast<int>((n + R - 1) / R);
@@ -831,7 +891,8 @@ static pcv_status step_run(pcv_ctx ctx, int64_t n_iter) {
     ctx->t += n_iter;
     return PCV_OK;
   }
-  const bool use_graph = ctx->graphs && !ctx->timing && ctx->path == PATH_MFMA && n_iter > 0;
+  const bool use_graph =
+      ctx->graphs && !ctx->timing && (ctx->path == PATH_MFMA || ctx->path == PATH_VALU_SPLIT) && n_iter > 0;
   if (use_graph) {
     TRY(capture_transition(ctx));
   }
@@ -1369,8 +1430,9 @@ std::string tune_key(pcv_ctx ctx) {
   std::string arch = "unknown";
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
   char buf[512];
+  const char* path = ctx->path == PATH_MFMA ? "mfma" : ctx->path == PATH_VALU_SPLIT ? "valu-split" : "valu";
   std::snprintf(buf, sizeof buf, "%s fam=%d prec=%d folds=%d n=%lld p=%lld C=%lld K=%d L=%d groups=%d arch=%s",
-                ctx->path == PATH_MFMA ? "mfma" : "valu", m.family, ctx->prec, m.fold_kind,
+                path, m.family, ctx->prec, m.fold_kind,
                 static_cast<long long>(m.n), static_cast<long long>(m.p), static_cast<long long>(m.C), m.K, m.L,
                 m.n_groups, arch.c_str());
   return buf;
@@ -1496,16 +1558,20 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   std::vector<TuneEntry> cache = cache_path ? cache_read(cache_path) : std::vector<TuneEntry>{};
   for (const TuneEntry& e : cache) {
     if (e.key != key) continue;
-    const bool valid = ctx->path == PATH_MFMA ? (e.cfg >= 1 && e.cfg <= ctx->n_tiles) : waves_ok(ctx, e.cfg);
+    const bool valid = ctx->path == PATH_MFMA        ? (e.cfg >= 1 && e.cfg <= ctx->n_tiles)
+                       : ctx->path == PATH_VALU_SPLIT ? e.cfg == ctx->n_splits
+                                                      : waves_ok(ctx, e.cfg);
     if (!valid) break;   // stale entry: tune again
     if (ctx->path == PATH_MFMA) TRY(apply_splits(ctx, e.cfg));
-    else TRY(apply_waves(ctx, e.cfg));
+    else if (ctx->path == PATH_VALU) TRY(apply_waves(ctx, e.cfg));
     if (config) *config = e.cfg;
     if (ms) *ms = e.ms;
     return PCV_OK;
   }
   std::vector<int> cand;
-  if (ctx->path == PATH_MFMA) {
+  if (ctx->path == PATH_VALU_SPLIT) {
+    cand.push_back(ctx->n_splits);   // the row-split shape is fixed at init: timed and recorded only
+  } else if (ctx->path == PATH_MFMA) {
     const int ns0 = ctx->n_splits, hi = std::min(64, ctx->n_tiles);
     for (int ns : {ns0 / 2, ns0 - 2, ns0 - 1, ns0, ns0 + 1, ns0 + 2, 2 * ns0}) {
       if (ns < 1 || ns > hi) continue;
@@ -1526,7 +1592,7 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   double best_ms = 0.0;
   pcv_status s = PCV_OK;
   for (int c : cand) {
-    s = ctx->path == PATH_MFMA ? apply_splits(ctx, c) : apply_waves(ctx, c);
+    s = ctx->path == PATH_MFMA ? apply_splits(ctx, c) : ctx->path == PATH_VALU ? apply_waves(ctx, c) : PCV_OK;
     double t = 0.0;
     if (s == PCV_OK) s = time_hot(ctx, reps, &t);
     if (s != PCV_OK) break;
@@ -1537,7 +1603,7 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   }
   ctx->timing = timing;
   if (s != PCV_OK) return s;
-  TRY(ctx->path == PATH_MFMA ? apply_splits(ctx, best) : apply_waves(ctx, best));
+  TRY(ctx->path == PATH_MFMA ? apply_splits(ctx, best) : ctx->path == PATH_VALU ? apply_waves(ctx, best) : PCV_OK);
   if (config) *config = best;
   if (ms) *ms = best_ms;
   if (cache_path) {

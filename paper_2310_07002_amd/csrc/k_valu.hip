@@ -9,7 +9,7 @@
 
 namespace pcv {
 
-enum { MODE_ITER = 0, MODE_GRAD = 1, MODE_LEAP = 2 };
+enum { MODE_ITER = 0, MODE_GRAD = 1, MODE_LEAP = 2, MODE_PART = 3 };
 
 struct ValuArgs {
   DevModel m;
@@ -18,6 +18,11 @@ struct ValuArgs {
   int n_iter;
   int mode;
   int n_steps;
+  // MODE_PART (row splits): partial sums [split][R][C], R = p (+ groups), and
+  // partial values [split][C]
+  double* Gpart;
+  double* Vpart;
+  int value;
 };
 
 template <typename T>
@@ -50,7 +55,8 @@ __device__ __forceinline__ T vell0(T y, T eta, T is2) {
 template <typename T, int FAM, int PB, bool VALUE>
 __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict__ Xv, int lane, int wave,
                                           int W, int64_t cc, int k, int elo, int ehi, T (&G)[PB],
-                                          double& val, char* smem, bool want_value = true) {
+                                          double& val, char* smem, bool want_value = true,
+                                          const int32_t* wave_rows = nullptr) {
   constexpr int JC = sizeof(T) == 8 ? 4 : 8;
   T* red = reinterpret_cast<T*>(smem);                                      // [W][JC][64]
   double* vred = reinterpret_cast<double*>(smem + sizeof(T) * W * JC * 64);  // [W][64]
@@ -75,7 +81,8 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
   for (int j = 0; j < PB; ++j) G[j] = T(0);
   val = 0.0;
   const T is2 = static_cast<T>(m.inv_sigma2);
-  const int64_t r0 = m.wave_rows[wave], r1 = m.wave_rows[wave + 1];
+  const int32_t* wr = wave_rows ? wave_rows : m.wave_rows;
+  const int64_t r0 = wr[wave], r1 = wr[wave + 1];
   int gcur = -1;
   T racc = T(0);
   for (int64_t i = r0; i < r1; ++i) {
@@ -254,6 +261,79 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_iter(ValuArgs a) {
   }
 }
 
+// Row-split gradient (few chains, many rows): workgroup (chain block x, split
+// y) evaluates its split's rows for its 64 chains; its W waves divide the
+// split (group-aligned for the hierarchical family).  Wave 0 writes the raw
+// partial sums -- sum x r per coefficient and, hierarchical, sum r per group
+// -- and the partial value; k_valu_finish adds the splits in a fixed order.
+template <typename T, int FAM, int PB>
+__global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_part(ValuArgs a) {
+  VALU_PROLOGUE
+  const int sp = blockIdx.y;
+  const int32_t* wr = m.wave_rows + static_cast<int64_t>(sp) * (W + 1);
+  if (a.value) grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem, true, wr);
+  else grad_eval<T, FAM, PB, false>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem, false, wr);
+  if (lead) {
+    constexpr int JC = sizeof(T) == 8 ? 4 : 8;
+    T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);
+    const T* rg = zt + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
+    const T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
+    const int64_t R = m.p + (FAM == FAM_HIER ? m.n_groups : 0);
+    double* out = a.Gpart + static_cast<int64_t>(sp) * R * m.C + c;
+#pragma nounroll
+    for (int64_t j = 0; j < m.p; ++j) out[j * m.C] = static_cast<double>(gfin[j * 64 + lane]);
+    if (FAM == FAM_HIER) {
+#pragma nounroll
+      for (int g = 0; g < m.n_groups; ++g) out[(m.p + g) * m.C] = static_cast<double>(rg[g * 64 + lane]);
+    }
+    if (a.value) a.Vpart[static_cast<int64_t>(sp) * m.C + c] = val;
+  }
+}
+
+// Sum of the row-split partials over the splits, in a fixed order, one thread
+// per (entry, chain), into the first split's slab (in place).
+__global__ void k_valu_sum(DevModel m, double* __restrict__ Gpart, int ns, int64_t R) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= R * m.C) return;
+  double v = 0.0;
+  for (int sp = 0; sp < ns; ++sp) v += Gpart[static_cast<int64_t>(sp) * R * m.C + idx];
+  Gpart[idx] = v;
+}
+
+// Prior and (hierarchical) the chain rule for mu, log tau and z over the
+// summed partials (ns slabs, normally 1 after k_valu_sum); then as k_reduce:
+// mode 0 writes g1, 1 and 2 apply a (last) leapfrog update.
+template <int FAM>
+__global__ void k_valu_finish(DevModel m, const double* __restrict__ Gpart, int ns, int mode) {
+  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (c >= m.C) return;
+  const int64_t R = m.p + (FAM == FAM_HIER ? m.n_groups : 0);
+  auto total = [&](int64_t j) {
+    double v = 0.0;
+    for (int sp = 0; sp < ns; ++sp) v += Gpart[(static_cast<int64_t>(sp) * R + j) * m.C + c];
+    return v;
+  };
+  auto emit = [&](int64_t j, double g) {
+    if (mode == 0) m.g1[j * m.C + c] = g;
+    else leapfrog_update(m, c, j, g, mode == 2);
+  };
+  for (int64_t j = 0; j < m.p; ++j) emit(j, total(j) + prior_grad(m, m.q1[j * m.C + c], j));
+  if (FAM == FAM_HIER) {
+    const double u = m.q1[(m.p + 1) * m.C + c];
+    const double tau = exp(u);
+    double gmu = 0.0, gu = 0.0;
+    for (int g = 0; g < m.n_groups; ++g) {
+      const double rs = total(m.p + g);
+      const double z = m.q1[(m.p + 2 + g) * m.C + c];
+      gmu += rs;
+      gu += z * rs;
+      emit(m.p + 2 + g, tau * rs - z);
+    }
+    emit(m.p, gmu - m.q1[m.p * m.C + c]);
+    emit(m.p + 1, tau * gu + prior_grad(m, u, m.p + 1));
+  }
+}
+
 // ----------------------------------------------------------------------------
 // Host-side dispatch
 // ----------------------------------------------------------------------------
@@ -274,8 +354,12 @@ int valu_pb(int64_t p, bool fp64) {
 }
 
 template <typename T, int FAM, int PB>
-static hipError_t launch_mode(const ValuArgs& a, int W, hipStream_t st, size_t smem, int nblk) {
+static hipError_t launch_mode(const ValuArgs& a, int W, hipStream_t st, size_t smem, int nblk, int ns = 1) {
   dim3 grid(nblk), block(64 * W);
+  if (a.mode == MODE_PART) {
+    hipLaunchKernelGGL((k_valu_part<T, FAM, PB>), dim3(nblk, ns), block, smem, st, a);
+    return hipGetLastError();
+  }
   if (a.mode == MODE_GRAD) hipLaunchKernelGGL((k_valu_grad<T, FAM, PB>), grid, block, smem, st, a);
   else if (a.mode == MODE_LEAP) hipLaunchKernelGGL((k_valu_leap<T, FAM, PB>), grid, block, smem, st, a);
   else hipLaunchKernelGGL((k_valu_iter<T, FAM, PB>), grid, block, smem, st, a);
@@ -283,13 +367,13 @@ static hipError_t launch_mode(const ValuArgs& a, int W, hipStream_t st, size_t s
 }
 
 template <typename T, int FAM>
-static hipError_t launch_fam(const ValuArgs& a, int pb, int W, hipStream_t st, size_t smem, int nblk) {
+static hipError_t launch_fam(const ValuArgs& a, int pb, int W, hipStream_t st, size_t smem, int nblk, int ns = 1) {
   switch (pb) {
-    case 8: return launch_mode<T, FAM, 8>(a, W, st, smem, nblk);
-    case 16: return launch_mode<T, FAM, 16>(a, W, st, smem, nblk);
-    case 32: return launch_mode<T, FAM, 32>(a, W, st, smem, nblk);
+    case 8: return launch_mode<T, FAM, 8>(a, W, st, smem, nblk, ns);
+    case 16: return launch_mode<T, FAM, 16>(a, W, st, smem, nblk, ns);
+    case 32: return launch_mode<T, FAM, 32>(a, W, st, smem, nblk, ns);
     case 64:
-      if constexpr (sizeof(T) == 4) return launch_mode<T, FAM, 64>(a, W, st, smem, nblk);
+      if constexpr (sizeof(T) == 4) return launch_mode<T, FAM, 64>(a, W, st, smem, nblk, ns);
       return hipErrorInvalidValue;
   }
   return hipErrorInvalidValue;
@@ -322,6 +406,54 @@ hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int
     }
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int ns, double* Gpart,
+                            double* Vpart, bool value, hipStream_t st) {
+  ValuArgs a{};
+  a.m = m;
+  a.Xv = Xv;
+  a.mode = MODE_PART;
+  a.Gpart = Gpart;
+  a.Vpart = Vpart;
+  a.value = value ? 1 : 0;
+  const int nblk = static_cast<int>((m.C + 63) / 64);
+  const size_t smem = valu_smem_bytes(fp64, W, m.family, m.n_groups);
+  if (fp64) {
+    switch (m.family) {
+      case FAM_GAUSS: return launch_fam<double, FAM_GAUSS>(a, pb, W, st, smem, nblk, ns);
+      case FAM_LOGIT: return launch_fam<double, FAM_LOGIT>(a, pb, W, st, smem, nblk, ns);
+      case FAM_POIS: return launch_fam<double, FAM_POIS>(a, pb, W, st, smem, nblk, ns);
+      case FAM_HIER: return launch_fam<double, FAM_HIER>(a, pb, W, st, smem, nblk, ns);
+    }
+  } else {
+    switch (m.family) {
+      case FAM_GAUSS: return launch_fam<float, FAM_GAUSS>(a, pb, W, st, smem, nblk, ns);
+      case FAM_LOGIT: return launch_fam<float, FAM_LOGIT>(a, pb, W, st, smem, nblk, ns);
+      case FAM_POIS: return launch_fam<float, FAM_POIS>(a, pb, W, st, smem, nblk, ns);
+      case FAM_HIER: return launch_fam<float, FAM_HIER>(a, pb, W, st, smem, nblk, ns);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_valu_sum(const DevModel& m, double* Gpart, int ns, hipStream_t st) {
+  const int64_t R = m.p + (m.family == FAM_HIER ? m.n_groups : 0);
+  hipLaunchKernelGGL(k_valu_sum, dim3(static_cast<unsigned>((R * m.C + 255) / 256)), dim3(256), 0, st, m, Gpart, ns,
+                     R);
+  return hipGetLastError();
+}
+
+hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, int ns, int mode, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>((m.C + 255) / 256)), block(256);
+  switch (m.family) {
+    case FAM_GAUSS: hipLaunchKernelGGL((k_valu_finish<FAM_GAUSS>), grid, block, 0, st, m, Gpart, ns, mode); break;
+    case FAM_LOGIT: hipLaunchKernelGGL((k_valu_finish<FAM_LOGIT>), grid, block, 0, st, m, Gpart, ns, mode); break;
+    case FAM_POIS: hipLaunchKernelGGL((k_valu_finish<FAM_POIS>), grid, block, 0, st, m, Gpart, ns, mode); break;
+    case FAM_HIER: hipLaunchKernelGGL((k_valu_finish<FAM_HIER>), grid, block, 0, st, m, Gpart, ns, mode); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace pcv
