@@ -393,8 +393,9 @@ class PCV:
 
     def autotune(self, cache_path: Optional[str] = None) -> dict:
         """Time candidate launch shapes of the hot kernel and keep the fastest
-        (row splits on the matrix-core path, waves per workgroup on the fused
-        VALU path); cache_path: JSON cache of tuned shapes."""
+        (row splits on the matrix-core and row-split VALU paths, waves per
+        workgroup on the fused VALU path); cache_path: JSON cache of tuned
+        shapes."""
         cfg = ctypes.c_int32()
         ms = ctypes.c_double()
         self._check(self._lib.pcv_autotune(self._ctx, os.fsencode(cache_path) if cache_path else None,

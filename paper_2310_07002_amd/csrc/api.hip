@@ -15,11 +15,12 @@ namespace pcv {
 // launchers (k_valu.hip, k_mfma.hip, k_common.hip)
 hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int mode, int64_t t0,
                        int n_iter, int n_steps, hipStream_t st);
-size_t valu_smem_bytes(bool fp64, int W, int family, int n_groups);
+size_t valu_smem_bytes(bool fp64, int W, int family, int n_groups, int pb);
+int valu_part_occupancy(bool fp64, int family, int pb, int W, size_t smem);
 hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int ns, double* Gpart,
-                            double* Vpart, bool value, hipStream_t st);
-hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, int ns, int mode, hipStream_t st);
-hipError_t launch_valu_sum(const DevModel& m, double* Gpart, int ns, hipStream_t st);
+                            double* Vpart, double* uscr, bool value, hipStream_t st);
+hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, const double* uscr, int ns, int mode,
+                              hipStream_t st);
 int valu_pb(int64_t p, bool fp64);
 hipError_t launch_mfma(const DevModel& m, const uint4* Xpk, const float* ty, const int32_t* tfid, float* Gpart,
                        double* Vpart, int n_tiles, int tiles_per_split, int n_splits, int fwd, bool value,
@@ -98,8 +99,10 @@ struct pcv_ctx_s {
   bool dead = false;
   uint64_t fingerprint = 0;   // of X, y, folds and groups (checkpoints)
   uint64_t fold_fp = 0;       // of the fold set alone (model comparison)
-  std::vector<int32_t> group_of_host;   // HIER: groups (VALU partitions when autotuning)
-  int split_cap = 0;                    // MFMA: row splits the partial buffers hold
+  int split_cap = 0;                    // row splits the partial buffers hold
+  int wave_rows_cap = 0;                // row-split VALU: splits the wave_rows buffer holds
+  double* uscr = nullptr;               // row-split VALU, hierarchical: [C] log tau of the partials
+  std::vector<int32_t> group_of_host;   // row-split VALU, hierarchical: groups of the rows
   std::vector<int32_t> test_ptr_host;   // [K+1] test rows of each fold (CSR)
   std::vector<int64_t> sq_ptr_host;     // [K+1] prefix sums of squared test-set sizes
 };
@@ -202,8 +205,8 @@ pcv_status split_partials(pcv_ctx ctx, bool value) {
   if (ctx->path == PATH_VALU_SPLIT) {
     if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
     timing_begin(ctx);
-    CK(launch_valu_part(m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, ctx->n_splits, ctx->Gpart64, ctx->Vpart, value,
-                        ctx->st));
+    CK(launch_valu_part(m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, ctx->n_splits, ctx->Gpart64, ctx->Vpart, ctx->uscr,
+                        value, ctx->st));
     timing_end(ctx);
     return PCV_OK;
   }
@@ -237,11 +240,10 @@ pcv_status split_partials(pcv_ctx ctx, bool value) {
 
 pcv_status split_reduce(pcv_ctx ctx, int mode) {
   if (ctx->path == PATH_VALU_SPLIT) {
-    // GLM: the split sums, prior and update per (coefficient, chain) thread;
-    // hierarchical: sum per (entry, chain) thread, then the chain rule per chain
+    // the split sums, prior (and hierarchical chain rule) and update per
+    // (entry, chain) thread
     if (ctx->m.family == FAM_HIER) {
-      CK(launch_valu_sum(ctx->m, ctx->Gpart64, ctx->n_splits, ctx->st));
-      CK(launch_valu_finish(ctx->m, ctx->Gpart64, 1, mode, ctx->st));
+      CK(launch_valu_finish(ctx->m, ctx->Gpart64, ctx->uscr, ctx->n_splits, mode, ctx->st));
     } else {
       CK(launch_reduce_f64(ctx->m, ctx->Gpart64, ctx->n_splits, mode, ctx->st));
     }
@@ -325,28 +327,83 @@ pcv_status capture_transition(pcv_ctx ctx) {
 // Row ranges [wr[w], wr[w+1]) of the W waves of a fused-VALU workgroup.  For
 // the hierarchical family the cuts are moved to group starts so each group
 // has one owner wave.
-std::vector<int32_t> valu_partition_range(int64_t lo, int64_t hi, int W, const int32_t* group_of) {
+// Even row partition of [lo, hi) over W waves: W + 1 boundaries.  Groups of
+// the hierarchical family may straddle wave boundaries (the kernels fold the
+// shared groups in a fixed order).
+std::vector<int32_t> valu_partition_range(int64_t lo, int64_t hi, int W) {
   std::vector<int32_t> wr(W + 1);
   for (int w = 0; w <= W; ++w) wr[w] = static_cast<int32_t>(lo + (hi - lo) * w / W);
-  if (group_of) {
-    for (int w = 1; w < W; ++w) {
-      int64_t i = std::max<int64_t>(wr[w], wr[w - 1]);
-      while (i > wr[w - 1] && i < hi && group_of[i] == group_of[i - 1]) --i;
-      if (i <= wr[w - 1]) {
-        i = std::max<int64_t>(wr[w], wr[w - 1]);
-        while (i < hi && i > lo && group_of[i] == group_of[i - 1]) ++i;
-      }
-      wr[w] = static_cast<int32_t>(std::min<int64_t>(i, hi));
-    }
-    for (int w = 1; w <= W; ++w) wr[w] = std::max(wr[w], wr[w - 1]);
-    wr[W] = static_cast<int32_t>(hi);
-  }
   return wr;
 }
 
-std::vector<int32_t> valu_partition(int64_t n, int W, const int32_t* group_of) {
-  return valu_partition_range(0, n, W, group_of);
+std::vector<int32_t> valu_partition(int64_t n, int W) { return valu_partition_range(0, n, W); }
+
+void drop_graph(pcv_ctx ctx);
+
+// Largest row-split count: each wave keeps at least 8 rows.
+int valu_split_max(pcv_ctx ctx) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(512, ctx->m.n / (8 * ctx->W))));
 }
+
+// Row-split VALU path: ns splits of the rows, W waves each (even
+// partitions), the splits spanning each group (hierarchical; rows are sorted
+// by group, and a group no split spans gets an empty range), and partial
+// buffers [ns][R][C] and [ns][C].
+pcv_status apply_valu_splits(pcv_ctx ctx, int ns) {
+  DevModel& m = ctx->m;
+  const int64_t n = m.n, C = m.C;
+  const int W = ctx->W;
+  std::vector<int32_t> wr;
+  for (int64_t sp = 0; sp < ns; ++sp) {
+    const std::vector<int32_t> part = valu_partition_range(n * sp / ns, n * (sp + 1) / ns, W);
+    wr.insert(wr.end(), part.begin(), part.end());
+  }
+  if (ns > ctx->wave_rows_cap) {
+    int32_t* d;
+    TRY(dalloc(ctx, &d, wr.size()));
+    ctx->wave_rows = d;
+    ctx->wave_rows_cap = ns;
+  }
+  CK(hipMemcpy(ctx->wave_rows, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice));
+  m.wave_rows = ctx->wave_rows;
+  const bool hier = m.family == FAM_HIER;
+  if (hier) {
+    const int32_t* go = ctx->group_of_host.data();
+    std::vector<int32_t> gs(2 * static_cast<size_t>(m.n_groups));
+    for (int g = 0; g < m.n_groups; ++g) {
+      gs[2 * g] = ns;
+      gs[2 * g + 1] = -1;
+    }
+    for (int64_t sp = 0; sp < ns; ++sp) {
+      const int64_t a = n * sp / ns, b = n * (sp + 1) / ns;
+      if (b <= a) continue;
+      for (int g = go[a]; g <= go[b - 1]; ++g) {
+        gs[2 * g] = std::min<int32_t>(gs[2 * g], static_cast<int32_t>(sp));
+        gs[2 * g + 1] = std::max<int32_t>(gs[2 * g + 1], static_cast<int32_t>(sp));
+      }
+    }
+    if (!m.gsplit) {
+      int32_t* d;
+      TRY(dalloc(ctx, &d, gs.size()));
+      m.gsplit = d;
+    }
+    CK(hipMemcpy(const_cast<int32_t*>(m.gsplit), gs.data(), sizeof(int32_t) * gs.size(), hipMemcpyHostToDevice));
+  }
+  if (hier && !ctx->uscr) TRY(dalloc(ctx, &ctx->uscr, static_cast<size_t>(C)));
+  if (ns > ctx->split_cap) {
+    double* g;
+    double* v;
+    TRY(dalloc(ctx, &g, static_cast<size_t>(ns) * m.d * C));
+    TRY(dalloc(ctx, &v, static_cast<size_t>(ns) * C));
+    ctx->Gpart64 = g;
+    ctx->Vpart = v;
+    ctx->split_cap = ns;
+  }
+  ctx->n_splits = ns;
+  drop_graph(ctx);
+  return PCV_OK;
+}
+
 
 bool finite_all(const double* a, int64_t n) {
   for (int64_t i = 0; i < n; ++i)
@@ -693,39 +750,44 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
       // W waves per workgroup, row splits so that (chain blocks x splits)
       // fills the GPU several times over while each wave keeps >= 32 rows
       int W = 4;
-      while (W > 1 && valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536) --W;
-      if (valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536)
+      while (W > 1 && valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups, ctx->pb) > 65536) --W;
+      if (valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups, ctx->pb) > 65536)
         return fail(ctx, PCV_ERR_UNSUPPORTED, "too many groups for the row-split path");
+      // Split count: workgroups run in rounds of (compute units x resident
+      // workgroups per unit); a workgroup costs its rows per wave plus about
+      // 32 rows' worth of set-up and partial-sum traffic.  Pick the count
+      // with the smallest rounds x cost (the fewest splits among ties).
       const int64_t chain_blocks = (C + 63) / 64;
-      const int64_t ns = std::max<int64_t>(1, std::min<int64_t>((2048 + chain_blocks - 1) / chain_blocks,
-                                                                n / (32 * W)));
+      int dev = 0, cus = 0;
+      CK(hipGetDevice(&dev));
+      CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      const int bpc = std::max(1, valu_part_occupancy(ctx->fp64, m.family, ctx->pb, W,
+                                                      valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups, ctx->pb)));
+      const int64_t cap = static_cast<int64_t>(std::max(1, cus)) * bpc;
+      int64_t ns = 1;
+      double best = 1e300;
       ctx->W = W;
-      ctx->n_splits = static_cast<int>(ns);
-      if (hier) ctx->group_of_host.assign(md->group_of, md->group_of + n);
-      std::vector<int32_t> wr;
-      for (int64_t sp = 0; sp < ns; ++sp) {
-        const std::vector<int32_t> part =
-            valu_partition_range(n * sp / ns, n * (sp + 1) / ns, W, hier ? md->group_of : nullptr);
-        wr.insert(wr.end(), part.begin(), part.end());
+      for (int64_t cand = 1; cand <= valu_split_max(ctx); ++cand) {
+        const double rounds = static_cast<double>((chain_blocks * cand + cap - 1) / cap);
+        const double cost = rounds * (std::ceil(static_cast<double>(n) / static_cast<double>(cand * W)) + 32.0);
+        if (cost < best - 1e-9) {
+          best = cost;
+          ns = cand;
+        }
       }
-      TRY(upload(ctx, &ctx->wave_rows, wr.data(), wr.size()));
-      m.wave_rows = ctx->wave_rows;
-      const size_t R = static_cast<size_t>(p) + (hier ? static_cast<size_t>(md->n_groups) : 0);
-      TRY(dalloc(ctx, &ctx->Gpart64, static_cast<size_t>(ns) * R * C));
-      double* vp;
-      TRY(dalloc(ctx, &vp, static_cast<size_t>(ns) * C));
-      ctx->Vpart = vp;
+      ctx->W = W;
+      if (hier) ctx->group_of_host.assign(md->group_of, md->group_of + n);
+      TRY(apply_valu_splits(ctx, static_cast<int>(ns)));
     } else {
     // waves per workgroup: enough rows per wave, LDS within 64 KB, and the
     // register budget of wide rows.
     int W = static_cast<int>(std::min<int64_t>(8, std::max<int64_t>(1, n / 64)));
     if (pb >= 32) W = std::min(W, 4);
-    while (W > 1 && valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536) --W;
-    if (valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups) > 65536)
+    while (W > 1 && valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups, ctx->pb) > 65536) --W;
+    if (valu_smem_bytes(ctx->fp64, W, m.family, m.n_groups, ctx->pb) > 65536)
       return fail(ctx, PCV_ERR_UNSUPPORTED, "too many groups for the fused path");
     ctx->W = W;
-    if (hier) ctx->group_of_host.assign(md->group_of, md->group_of + n);
-    const std::vector<int32_t> wr = valu_partition(n, W, hier ? md->group_of : nullptr);
+    const std::vector<int32_t> wr = valu_partition(n, W);
     TRY(dalloc(ctx, &ctx->wave_rows, 9));   // room for any W <= 8 (autotuning)
     CK(hipMemcpy(ctx->wave_rows, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice));
     m.wave_rows = ctx->wave_rows;
@@ -1510,13 +1572,12 @@ pcv_status apply_splits(pcv_ctx ctx, int ns) {
 
 bool waves_ok(pcv_ctx ctx, int W) {
   return W >= 1 && W <= 8 && !(ctx->pb >= 32 && W > 4) && ctx->m.n / W >= 8 &&
-         valu_smem_bytes(ctx->fp64, W, ctx->m.family, ctx->m.n_groups) <= 65536;
+         valu_smem_bytes(ctx->fp64, W, ctx->m.family, ctx->m.n_groups, ctx->pb) <= 65536;
 }
 
 // VALU path: W waves per workgroup, each owning a range of rows.
 pcv_status apply_waves(pcv_ctx ctx, int W) {
-  const std::vector<int32_t> wr =
-      valu_partition(ctx->m.n, W, ctx->group_of_host.empty() ? nullptr : ctx->group_of_host.data());
+  const std::vector<int32_t> wr = valu_partition(ctx->m.n, W);
   CK(hipMemcpy(ctx->wave_rows, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice));
   ctx->W = W;
   return PCV_OK;
@@ -1533,7 +1594,11 @@ pcv_status time_hot(pcv_ctx ctx, int reps, double* ms) {
       CK(launch_valu(ctx->m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, 1, 0, 0, 0, ctx->st));
       return PCV_OK;
     }
-    return split_partials(ctx, false);
+    TRY(split_partials(ctx, false));
+    // row-split VALU: the split count also sets the reduction's work, so the
+    // reduction (mode 0: gradient into the scratch g1) is timed with it
+    if (ctx->path == PATH_VALU_SPLIT) TRY(split_reduce(ctx, 0));
+    return PCV_OK;
   };
   pcv_status s = launch();
   if (s == PCV_OK && hipEventRecord(a, ctx->st) != hipSuccess) s = PCV_ERR_DEVICE;
@@ -1559,18 +1624,22 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   for (const TuneEntry& e : cache) {
     if (e.key != key) continue;
     const bool valid = ctx->path == PATH_MFMA        ? (e.cfg >= 1 && e.cfg <= ctx->n_tiles)
-                       : ctx->path == PATH_VALU_SPLIT ? e.cfg == ctx->n_splits
+                       : ctx->path == PATH_VALU_SPLIT ? (e.cfg >= 1 && e.cfg <= valu_split_max(ctx))
                                                       : waves_ok(ctx, e.cfg);
     if (!valid) break;   // stale entry: tune again
     if (ctx->path == PATH_MFMA) TRY(apply_splits(ctx, e.cfg));
-    else if (ctx->path == PATH_VALU) TRY(apply_waves(ctx, e.cfg));
+    else if (ctx->path == PATH_VALU_SPLIT) TRY(apply_valu_splits(ctx, e.cfg));
+    else TRY(apply_waves(ctx, e.cfg));
     if (config) *config = e.cfg;
     if (ms) *ms = e.ms;
     return PCV_OK;
   }
   std::vector<int> cand;
   if (ctx->path == PATH_VALU_SPLIT) {
-    cand.push_back(ctx->n_splits);   // the row-split shape is fixed at init: timed and recorded only
+    const int ns0 = ctx->n_splits;
+    for (int ns : {ns0 / 2, (3 * ns0) / 4, ns0, (3 * ns0) / 2, 2 * ns0})
+      if (ns >= 1 && ns <= valu_split_max(ctx) && std::find(cand.begin(), cand.end(), ns) == cand.end())
+        cand.push_back(ns);
   } else if (ctx->path == PATH_MFMA) {
     const int ns0 = ctx->n_splits, hi = std::min(64, ctx->n_tiles);
     for (int ns : {ns0 / 2, ns0 - 2, ns0 - 1, ns0, ns0 + 1, ns0 + 2, 2 * ns0}) {
@@ -1592,7 +1661,8 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   double best_ms = 0.0;
   pcv_status s = PCV_OK;
   for (int c : cand) {
-    s = ctx->path == PATH_MFMA ? apply_splits(ctx, c) : ctx->path == PATH_VALU ? apply_waves(ctx, c) : PCV_OK;
+    s = ctx->path == PATH_MFMA ? apply_splits(ctx, c) : ctx->path == PATH_VALU ? apply_waves(ctx, c)
+                                                                               : apply_valu_splits(ctx, c);
     double t = 0.0;
     if (s == PCV_OK) s = time_hot(ctx, reps, &t);
     if (s != PCV_OK) break;
@@ -1603,7 +1673,9 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   }
   ctx->timing = timing;
   if (s != PCV_OK) return s;
-  TRY(ctx->path == PATH_MFMA ? apply_splits(ctx, best) : ctx->path == PATH_VALU ? apply_waves(ctx, best) : PCV_OK);
+  TRY(ctx->path == PATH_MFMA   ? apply_splits(ctx, best)
+      : ctx->path == PATH_VALU ? apply_waves(ctx, best)
+                               : apply_valu_splits(ctx, best));
   if (config) *config = best;
   if (ms) *ms = best_ms;
   if (cache_path) {

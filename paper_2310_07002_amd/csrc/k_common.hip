@@ -10,12 +10,6 @@ static inline int nblocks(int64_t n, int tpb = TPB) { return static_cast<int>((n
 
 // ---- transition pieces -----------------------------------------------------
 
-__global__ void k_momentum(DevModel m, int64_t t) {
-  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (t < 0) t = *m.t_dev;
-  if (c < m.C) momentum_and_first_drift(m, c, t);
-}
-
 // Advance the device-side transition counter (last node of a captured transition).
 __global__ void k_tick(DevModel m) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *m.t_dev += 1;
@@ -47,13 +41,97 @@ __global__ void k_value_finish(DevModel m, const double* Vpart, int n_splits) {
   if (c < m.C) m.logp1[c] = value_finish(m, Vpart, n_splits, c);
 }
 
-template <int FAM>
-__global__ void k_accept(DevModel m, const double* Vpart, int n_splits, int64_t t) {
-  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (c >= m.C) return;
+// ---- block-wide transition pieces of the split paths -------------------------
+// One workgroup per 64 chains (lane = chain); its Y waves share each chain's
+// loops over coordinates, value partials and test rows, and the per-wave
+// partial sums are added in a fixed order (bit-reproducible).
+
+constexpr int WIDE_MAX_Y = 16;
+
+// Momentum refresh, first half kick and drift; the waves take the Philox
+// blocks jb = y, y + Y, ...
+__global__ __launch_bounds__(64 * WIDE_MAX_Y) void k_momentum(DevModel m, int64_t t) {
+  __shared__ double red[WIDE_MAX_Y][64];
+  const int lane = threadIdx.x & 63, y = threadIdx.x >> 6, Y = blockDim.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const bool valid = c < m.C;
   if (t < 0) t = *m.t_dev;
-  m.logp1[c] = value_finish(m, Vpart, n_splits, c);
-  accept_and_accumulate<FAM>(m, c, t);
+  double k0 = 0.0;
+  if (valid)
+    for (int64_t jb = y; 2 * jb < m.d; jb += Y) momentum_pair(m, c, t, jb, k0);
+  red[y][lane] = k0;
+  __syncthreads();
+  if (y == 0 && valid) {
+    double s = 0.0;
+    for (int w = 0; w < Y; ++w) s += red[w][lane];
+    m.h0[c] = -m.logp0[c] + s;
+  }
+}
+
+// Metropolis test and accumulation.  Phase 1 (all waves): value partials,
+// prior, kinetic energy and the log predictive of the proposal q1 over a
+// contiguous share of the fold's test rows.  Phase 2 (wave 0): log pi(q1),
+// the test, logp0 and s0 (the proposal's log predictive when accepted).
+// Phase 3 (all waves): q0, g0 := q1, g1 for accepted chains.  Phase 4
+// (wave 0): accumulation, which reads the selected q0 for the scores.
+constexpr int ACCEPT_MAX_Y = 8;   // the scores' predictive draws need the registers of 512-thread groups
+template <int FAM>
+__global__ __launch_bounds__(64 * ACCEPT_MAX_Y) void k_accept(DevModel m, const double* __restrict__ Vpart,
+                                                              int n_splits, int64_t t) {
+  __shared__ double red[4][ACCEPT_MAX_Y][64];
+  __shared__ int acc_s[64];
+  const int lane = threadIdx.x & 63, y = threadIdx.x >> 6, Y = blockDim.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const bool valid = c < m.C;
+  const int64_t cc = valid ? c : m.C - 1;
+  if (t < 0) t = *m.t_dev;
+  double v = 0.0, pq = 0.0, k1 = 0.0, lp = 0.0;
+  for (int s = y; s < n_splits; s += Y) v += Vpart[static_cast<int64_t>(s) * m.C + cc];
+  for (int64_t j = y; j < m.d; j += Y) {
+    const int64_t o = j * m.C + cc;
+    pq += prior_term(m, m.q1[o], j);
+    const double p = m.pm[o];
+    k1 += 0.5 * m.minv[j] * p * p;
+  }
+  const int k = static_cast<int>(cc / m.L);
+  const int beg = m.test_ptr[k], nt = m.test_ptr[k + 1] - beg;
+  lp = log_pred_rows<FAM>(m, m.q1, cc, beg + static_cast<int>(static_cast<int64_t>(nt) * y / Y),
+                          beg + static_cast<int>(static_cast<int64_t>(nt) * (y + 1) / Y));
+  red[0][y][lane] = v;
+  red[1][y][lane] = pq;
+  red[2][y][lane] = k1;
+  red[3][y][lane] = lp;
+  __syncthreads();
+  bool accepted = false, divergent = false;
+  if (y == 0) {
+    v = pq = k1 = lp = 0.0;
+    for (int w = 0; w < Y; ++w) {
+      v += red[0][w][lane];
+      pq += red[1][w][lane];
+      k1 += red[2][w][lane];
+      lp += red[3][w][lane];
+    }
+    if (valid) {
+      const double logp1 = v + m.fold_const[k] + pq;
+      m.logp1[c] = logp1;
+      metropolis(m, c, t, k1, accepted, divergent);
+      if (accepted) {
+        m.logp0[c] = logp1;
+        m.s0[c] = lp;
+      }
+    }
+    acc_s[lane] = accepted ? 1 : 0;
+  }
+  __syncthreads();
+  if (valid && acc_s[lane]) {
+    for (int64_t j = y; j < m.d; j += Y) {
+      const int64_t o = j * m.C + c;
+      m.q0[o] = m.q1[o];
+      m.g0[o] = m.g1[o];
+    }
+  }
+  __syncthreads();
+  if (y == 0 && valid) record_draw<FAM>(m, c, t, accepted, divergent);
 }
 
 // Log predictive at q0 for every chain (initialisation and set_state).
@@ -369,10 +447,6 @@ __global__ void k_kick_drift(DevModel m) {
     }                                                                                            \
   } while (0)
 
-hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st) {
-  hipLaunchKernelGGL(k_momentum, dim3(nblocks(m.C)), dim3(TPB), 0, st, m, t);
-  return hipGetLastError();
-}
 hipError_t launch_tick(const DevModel& m, hipStream_t st) {
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, m);
   return hipGetLastError();
@@ -393,8 +467,22 @@ hipError_t launch_value_finish(const DevModel& m, const double* V, int ns, hipSt
   hipLaunchKernelGGL(k_value_finish, dim3(nblocks(m.C)), dim3(TPB), 0, st, m, V, ns);
   return hipGetLastError();
 }
+// Waves per workgroup of the block-wide kernels: enough waves to cover the
+// chips' SIMDs when the chains are few.
+int wide_waves(int64_t C) {
+  const int64_t blocks = (C + 63) / 64;
+  if (blocks < 64) return WIDE_MAX_Y;
+  if (blocks < 256) return 8;
+  return 4;
+}
+hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st) {
+  const int Y = wide_waves(m.C);
+  hipLaunchKernelGGL(k_momentum, dim3(nblocks(m.C, 64)), dim3(64 * Y), 0, st, m, t);
+  return hipGetLastError();
+}
 hipError_t launch_accept(const DevModel& m, const double* V, int ns, int64_t t, hipStream_t st) {
-  PCV_FAM_DISPATCH(m.family, k_accept, dim3(nblocks(m.C)), dim3(TPB), st, m, V, ns, t);
+  const int Y = std::min(wide_waves(m.C), ACCEPT_MAX_Y);
+  PCV_FAM_DISPATCH(m.family, k_accept, dim3(nblocks(m.C, 64)), dim3(64 * Y), st, m, V, ns, t);
   return hipGetLastError();
 }
 hipError_t launch_logpred(const DevModel& m, hipStream_t st) {

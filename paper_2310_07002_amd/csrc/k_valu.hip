@@ -23,6 +23,7 @@ struct ValuArgs {
   double* Gpart;
   double* Vpart;
   int value;
+  double* uscr;   // hierarchical: [C] log tau at the evaluation point (split 0 writes it)
 };
 
 template <typename T>
@@ -52,61 +53,90 @@ __device__ __forceinline__ T vell0(T y, T eta, T is2) {
 // G (beta part) and, for the hierarchical family, the per-group residual sums
 // in LDS rg; val (wave 0) holds the masked log-likelihood sum without row
 // constants.
+// Coefficients per round of the cross-wave gradient reduction (LDS [W][JC][64]).
+template <typename T, int PB>
+__host__ __device__ constexpr int valu_jc() {
+  return (sizeof(T) == 8 ? 4 : 8) < PB ? (sizeof(T) == 8 ? 4 : 8) : PB;
+}
+
+// Groups [glo, ghi] spanned by the rows [wr[0], wr[W]) of a workgroup (rows
+// are sorted by group); empty range (glo > ghi) when it has no rows.
+__device__ __forceinline__ void block_groups(const DevModel& m, const int32_t* wr, int W, int& glo, int& ghi) {
+  glo = 0;
+  ghi = -1;
+  if (wr[W] > wr[0]) {
+    glo = m.group_of[wr[0]];
+    ghi = m.group_of[wr[W] - 1];
+  }
+}
+
 template <typename T, int FAM, int PB, bool VALUE>
 __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict__ Xv, int lane, int wave,
                                           int W, int64_t cc, int k, int elo, int ehi, T (&G)[PB],
                                           double& val, char* smem, bool want_value = true,
                                           const int32_t* wave_rows = nullptr) {
-  constexpr int JC = sizeof(T) == 8 ? 4 : 8;
+  constexpr int JC = valu_jc<T, PB>();
   T* red = reinterpret_cast<T*>(smem);                                      // [W][JC][64]
   double* vred = reinterpret_cast<double*>(smem + sizeof(T) * W * JC * 64);  // [W][64]
   T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);  // [G][64]
   T* rg = zt + (FAM == FAM_HIER ? m.n_groups * 64 : 0);                      // [G][64]
   T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);                    // [PB][64]
+  T* ef = gfin + PB * 64;                                                     // [W][2][64]
+  int* eg = reinterpret_cast<int*>(ef + (FAM == FAM_HIER ? W * 2 * 64 : 0));  // [W][2]
 
+  const int32_t* wr = wave_rows ? wave_rows : m.wave_rows;
   T th[PB];
 #pragma unroll
   for (int j = 0; j < PB; ++j) th[j] = (j < m.p) ? static_cast<T>(m.q1[j * m.C + cc]) : T(0);
   T mu = 0;
   if (FAM == FAM_HIER) {
+    // tau z_g only for the groups of this workgroup's rows; rg cleared for all
     mu = static_cast<T>(m.q1[m.p * m.C + cc]);
     const T tau = static_cast<T>(exp(m.q1[(m.p + 1) * m.C + cc]));
-    for (int g = wave; g < m.n_groups; g += W) {
+    int glo, ghi;
+    block_groups(m, wr, W, glo, ghi);
+    for (int g = glo + wave; g <= ghi; g += W)
       zt[g * 64 + lane] = tau * static_cast<T>(m.q1[(m.p + 2 + g) * m.C + cc]);
-      rg[g * 64 + lane] = T(0);
-    }
+    for (int g = wave; g < m.n_groups; g += W) rg[g * 64 + lane] = T(0);
     __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < PB; ++j) G[j] = T(0);
   val = 0.0;
   const T is2 = static_cast<T>(m.inv_sigma2);
-  const int32_t* wr = wave_rows ? wave_rows : m.wave_rows;
   const int64_t r0 = wr[wave], r1 = wr[wave + 1];
-  int gcur = -1;
-  T racc = T(0);
-  for (int64_t i = r0; i < r1; ++i) {
-    const T* xr = Xv + i * PB;
-    T xv[PB];
-#pragma unroll
-    for (int j = 0; j < PB; ++j) xv[j] = xr[j];
+  // Hierarchical: rows are sorted by group.  A group that starts and ends
+  // inside this wave's rows is this wave's alone and goes straight to rg; the
+  // wave's first and last groups may be shared with its neighbours and go to
+  // edge slots, added to rg in a fixed order after the loop.
+  int gcur = -1, gfirst = -1;
+  T racc = T(0), zcur = T(0);
+  // One row: its coefficients xv, response y, group g and fold id f (the
+  // fold id is used by index-coded folds only).
+  auto row = [&](int64_t i, const T (&xv)[PB], T y, int g, int f) {
     T eta = T(0);
 #pragma unroll
     for (int j = 0; j < PB; ++j) eta += xv[j] * th[j];
     if (FAM == FAM_HIER) {
-      const int g = m.group_of[i];
       if (g != gcur) {
-        if (gcur >= 0) rg[gcur * 64 + lane] += racc;
+        if (gcur >= 0) {
+          if (gfirst < 0) {
+            gfirst = gcur;
+            ef[(wave * 2) * 64 + lane] = racc;
+          } else {
+            rg[gcur * 64 + lane] += racc;
+          }
+        }
         gcur = g;
         racc = T(0);
+        zcur = zt[g * 64 + lane];
       }
-      eta += mu + zt[g * 64 + lane];
+      eta += mu + zcur;
     }
     bool train;
-    if (m.fold_kind == PCV_FOLDS_INDEX) train = m.fold_index[i] != k;
+    if (m.fold_kind == PCV_FOLDS_INDEX) train = f != k;
     else if (m.fold_kind == PCV_FOLDS_INTERVALS) train = (i < elo) || (i >= ehi);
     else train = m.roles[static_cast<int64_t>(k) * m.n + i] == 1;
-    const T y = ValuY<T>::get(m, i);
     const T r = train ? vresid<FAM, T>(y, eta, is2) : T(0);
 #pragma unroll
     for (int j = 0; j < PB; ++j) G[j] += xv[j] * r;
@@ -114,8 +144,40 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
     if (VALUE && want_value) {
       if (train) val += static_cast<double>(vell0<FAM, T>(y, eta, is2));
     }
+  };
+  for (int64_t i = r0; i < r1; ++i) {
+    const T* xr = Xv + i * PB;
+    T xv[PB];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) xv[j] = xr[j];
+    row(i, xv, ValuY<T>::get(m, i), FAM == FAM_HIER ? m.group_of[i] : 0,
+        m.fold_kind == PCV_FOLDS_INDEX ? m.fold_index[i] : 0);
   }
-  if (FAM == FAM_HIER && gcur >= 0) rg[gcur * 64 + lane] += racc;
+  if (FAM == FAM_HIER) {
+    int glast = -1;
+    if (gcur >= 0) {
+      if (gfirst < 0) {
+        gfirst = gcur;
+        ef[(wave * 2) * 64 + lane] = racc;
+      } else {
+        glast = gcur;
+        ef[(wave * 2 + 1) * 64 + lane] = racc;
+      }
+    }
+    if (lane == 0) {
+      eg[2 * wave] = gfirst;
+      eg[2 * wave + 1] = glast;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int w = 0; w < W; ++w) {
+        const int g0 = eg[2 * w], g1 = eg[2 * w + 1];
+        if (g0 >= 0) rg[g0 * 64 + lane] += ef[(2 * w) * 64 + lane];
+        if (g1 >= 0) rg[g1 * 64 + lane] += ef[(2 * w + 1) * 64 + lane];
+      }
+    }
+    __syncthreads();
+  }
 
   // Cross-wave reduction in a fixed order (bit-reproducible).
 #pragma unroll
@@ -153,7 +215,7 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
 // out of the leapfrog loop and exhausts the register file.
 template <typename T, int FAM, int PB, typename Emit>
 __device__ __forceinline__ void finish_chain(const DevModel& m, int64_t c, int lane, char* smem, int W, Emit emit) {
-  constexpr int JC = sizeof(T) == 8 ? 4 : 8;
+  constexpr int JC = valu_jc<T, PB>();
   T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);
   T* rg = zt + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
   const T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
@@ -263,9 +325,10 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_iter(ValuArgs a) {
 
 // Row-split gradient (few chains, many rows): workgroup (chain block x, split
 // y) evaluates its split's rows for its 64 chains; its W waves divide the
-// split (group-aligned for the hierarchical family).  Wave 0 writes the raw
-// partial sums -- sum x r per coefficient and, hierarchical, sum r per group
-// -- and the partial value; k_valu_finish adds the splits in a fixed order.
+// split.  Wave 0 writes the raw partial sums [split][d][C] -- sum x r per
+// coefficient and, hierarchical, the group sums and their mu and log tau
+// shares -- and the partial value; the splits are added in a fixed order
+// by k_reduce (GLMs) or k_valu_finish (hierarchical).
 template <typename T, int FAM, int PB>
 __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_part(ValuArgs a) {
   VALU_PROLOGUE
@@ -274,78 +337,93 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_part(ValuArgs a) {
   if (a.value) grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem, true, wr);
   else grad_eval<T, FAM, PB, false>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem, false, wr);
   if (lead) {
-    constexpr int JC = sizeof(T) == 8 ? 4 : 8;
+    constexpr int JC = valu_jc<T, PB>();
     T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);
     const T* rg = zt + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
     const T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
-    const int64_t R = m.p + (FAM == FAM_HIER ? m.n_groups : 0);
-    double* out = a.Gpart + static_cast<int64_t>(sp) * R * m.C + c;
+    double* out = a.Gpart + static_cast<int64_t>(sp) * m.d * m.C + c;
 #pragma nounroll
     for (int64_t j = 0; j < m.p; ++j) out[j * m.C] = static_cast<double>(gfin[j * 64 + lane]);
     if (FAM == FAM_HIER) {
+      // group sums r_g of this split's groups only (the finish kernel reads
+      // group g from the splits that span it), and the split's shares of the
+      // mu and log tau likelihood gradients, sum_g r_g and sum_g z_g r_g
+      int glo, ghi;
+      block_groups(m, wr, W, glo, ghi);
+      double sr = 0.0, szr = 0.0;
 #pragma nounroll
-      for (int g = 0; g < m.n_groups; ++g) out[(m.p + g) * m.C] = static_cast<double>(rg[g * 64 + lane]);
+      for (int g = glo; g <= ghi; ++g) {
+        const double r = static_cast<double>(rg[g * 64 + lane]);
+        out[(m.p + 2 + g) * m.C] = r;
+        sr += r;
+        szr += m.q1[(m.p + 2 + g) * m.C + c] * r;
+      }
+      out[m.p * m.C] = sr;
+      out[(m.p + 1) * m.C] = szr;
+      if (sp == 0) a.uscr[c] = m.q1[(m.p + 1) * m.C + c];
     }
     if (a.value) a.Vpart[static_cast<int64_t>(sp) * m.C + c] = val;
   }
 }
 
-// Sum of the row-split partials over the splits, in a fixed order, one thread
-// per (entry, chain), into the first split's slab (in place).
-__global__ void k_valu_sum(DevModel m, double* __restrict__ Gpart, int ns, int64_t R) {
+// Hierarchical family, row splits: one thread per (entry, chain) of the
+// [split][d][C] partials.  Coefficients, mu and log tau add every split,
+// group g the splits that span it (gsplit), in split order; then the prior
+// and the chain rule (mu: sum r - mu; log tau: tau sum z r + prior; z_g:
+// tau r_g - z_g) with tau from uscr, the log tau the partials were taken
+// at (q1 itself may already be updated by the log tau thread).  mode 0
+// writes g1, 1 and 2 apply a (last) leapfrog update.
+__global__ void k_valu_finish(DevModel m, const double* __restrict__ Gpart, const double* __restrict__ uscr, int ns,
+                              int mode) {
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (idx >= R * m.C) return;
-  double v = 0.0;
-  for (int sp = 0; sp < ns; ++sp) v += Gpart[static_cast<int64_t>(sp) * R * m.C + idx];
-  Gpart[idx] = v;
-}
-
-// Prior and (hierarchical) the chain rule for mu, log tau and z over the
-// summed partials (ns slabs, normally 1 after k_valu_sum); then as k_reduce:
-// mode 0 writes g1, 1 and 2 apply a (last) leapfrog update.
-template <int FAM>
-__global__ void k_valu_finish(DevModel m, const double* __restrict__ Gpart, int ns, int mode) {
-  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (c >= m.C) return;
-  const int64_t R = m.p + (FAM == FAM_HIER ? m.n_groups : 0);
-  auto total = [&](int64_t j) {
-    double v = 0.0;
-    for (int sp = 0; sp < ns; ++sp) v += Gpart[(static_cast<int64_t>(sp) * R + j) * m.C + c];
-    return v;
-  };
-  auto emit = [&](int64_t j, double g) {
-    if (mode == 0) m.g1[j * m.C + c] = g;
-    else leapfrog_update(m, c, j, g, mode == 2);
-  };
-  for (int64_t j = 0; j < m.p; ++j) emit(j, total(j) + prior_grad(m, m.q1[j * m.C + c], j));
-  if (FAM == FAM_HIER) {
-    const double u = m.q1[(m.p + 1) * m.C + c];
-    const double tau = exp(u);
-    double gmu = 0.0, gu = 0.0;
-    for (int g = 0; g < m.n_groups; ++g) {
-      const double rs = total(m.p + g);
-      const double z = m.q1[(m.p + 2 + g) * m.C + c];
-      gmu += rs;
-      gu += z * rs;
-      emit(m.p + 2 + g, tau * rs - z);
-    }
-    emit(m.p, gmu - m.q1[m.p * m.C + c]);
-    emit(m.p + 1, tau * gu + prior_grad(m, u, m.p + 1));
+  if (idx >= m.d * m.C) return;
+  const int64_t j = idx / m.C, c = idx - j * m.C;
+  const int64_t dC = m.d * m.C;
+  int s0 = 0, s1 = ns - 1;
+  if (j >= m.p + 2) {
+    const int64_t g = j - m.p - 2;
+    s0 = m.gsplit[2 * g];
+    s1 = m.gsplit[2 * g + 1];
   }
+  const double* gp = Gpart + idx;
+  double v = 0.0;
+  int sp = s0;
+  for (; sp + 8 <= s1 + 1; sp += 8) {   // loads issued eight at a time, added in split order
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = gp[(sp + u) * dC];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += t[u];
+  }
+  for (; sp <= s1; ++sp) v += gp[sp * dC];
+  double g;
+  if (j < m.p) {
+    g = v + prior_grad(m, m.q1[idx], j);
+  } else if (j == m.p) {
+    g = v - m.q1[idx];
+  } else {
+    const double u = uscr[c];
+    const double tau = exp(u);
+    g = j == m.p + 1 ? tau * v + prior_grad(m, u, j) : tau * v - m.q1[idx];
+  }
+  if (mode == 0) m.g1[idx] = g;
+  else leapfrog_update(m, c, j, g, mode == 2);
 }
 
 // ----------------------------------------------------------------------------
 // Host-side dispatch
 // ----------------------------------------------------------------------------
-size_t valu_smem_bytes(bool fp64, int W, int family, int n_groups) {
+size_t valu_smem_bytes(bool fp64, int W, int family, int n_groups, int pb) {
   const size_t tsz = fp64 ? 8 : 4;
-  const size_t jc = fp64 ? 4 : 8;
+  const size_t jc = std::min<size_t>(fp64 ? 4 : 8, static_cast<size_t>(pb));
   size_t b = tsz * W * jc * 64 + 8 * W * 64;
-  if (family == FAM_HIER) b += 2 * tsz * n_groups * 64;
-  return b + tsz * 64 * 64;   // gfin, sized for the widest PB
+  b += tsz * static_cast<size_t>(pb) * 64;   // gfin
+  if (family == FAM_HIER) b += 2 * tsz * n_groups * 64 + 2 * tsz * W * 64 + 8 * W;   // zt, rg, edge slots
+  return b;
 }
 
 int valu_pb(int64_t p, bool fp64) {
+  if (p <= 4) return 4;
   if (p <= 8) return 8;
   if (p <= 16) return 16;
   if (p <= 32) return 32;
@@ -369,6 +447,7 @@ static hipError_t launch_mode(const ValuArgs& a, int W, hipStream_t st, size_t s
 template <typename T, int FAM>
 static hipError_t launch_fam(const ValuArgs& a, int pb, int W, hipStream_t st, size_t smem, int nblk, int ns = 1) {
   switch (pb) {
+    case 4: return launch_mode<T, FAM, 4>(a, W, st, smem, nblk, ns);
     case 8: return launch_mode<T, FAM, 8>(a, W, st, smem, nblk, ns);
     case 16: return launch_mode<T, FAM, 16>(a, W, st, smem, nblk, ns);
     case 32: return launch_mode<T, FAM, 32>(a, W, st, smem, nblk, ns);
@@ -389,7 +468,7 @@ hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int
   a.mode = mode;
   a.n_steps = n_steps;
   const int nblk = static_cast<int>((m.C + 63) / 64);
-  const size_t smem = valu_smem_bytes(fp64, W, m.family, m.n_groups);
+  const size_t smem = valu_smem_bytes(fp64, W, m.family, m.n_groups, pb);
   if (fp64) {
     switch (m.family) {
       case FAM_GAUSS: return launch_fam<double, FAM_GAUSS>(a, pb, W, st, smem, nblk);
@@ -409,16 +488,17 @@ hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int
 }
 
 hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int ns, double* Gpart,
-                            double* Vpart, bool value, hipStream_t st) {
+                            double* Vpart, double* uscr, bool value, hipStream_t st) {
   ValuArgs a{};
   a.m = m;
   a.Xv = Xv;
   a.mode = MODE_PART;
   a.Gpart = Gpart;
   a.Vpart = Vpart;
+  a.uscr = uscr;
   a.value = value ? 1 : 0;
   const int nblk = static_cast<int>((m.C + 63) / 64);
-  const size_t smem = valu_smem_bytes(fp64, W, m.family, m.n_groups);
+  const size_t smem = valu_smem_bytes(fp64, W, m.family, m.n_groups, pb);
   if (fp64) {
     switch (m.family) {
       case FAM_GAUSS: return launch_fam<double, FAM_GAUSS>(a, pb, W, st, smem, nblk, ns);
@@ -437,22 +517,40 @@ hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_valu_sum(const DevModel& m, double* Gpart, int ns, hipStream_t st) {
-  const int64_t R = m.p + (m.family == FAM_HIER ? m.n_groups : 0);
-  hipLaunchKernelGGL(k_valu_sum, dim3(static_cast<unsigned>((R * m.C + 255) / 256)), dim3(256), 0, st, m, Gpart, ns,
-                     R);
-  return hipGetLastError();
+// Workgroups of k_valu_part per compute unit (registers, LDS and threads),
+// from the runtime's occupancy calculator; 0 if unknown.
+template <typename T, int FAM>
+static int part_occupancy_fam(int pb, int W, size_t smem) {
+  const void* f = nullptr;
+  switch (pb) {
+    case 4: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 4>); break;
+    case 8: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 8>); break;
+    case 16: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 16>); break;
+    case 32: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 32>); break;
+    case 64:
+      if constexpr (sizeof(T) == 4) f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 64>);
+      break;
+  }
+  int nb = 0;
+  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * W, smem) != hipSuccess) return 0;
+  return nb;
 }
 
-hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, int ns, int mode, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>((m.C + 255) / 256)), block(256);
-  switch (m.family) {
-    case FAM_GAUSS: hipLaunchKernelGGL((k_valu_finish<FAM_GAUSS>), grid, block, 0, st, m, Gpart, ns, mode); break;
-    case FAM_LOGIT: hipLaunchKernelGGL((k_valu_finish<FAM_LOGIT>), grid, block, 0, st, m, Gpart, ns, mode); break;
-    case FAM_POIS: hipLaunchKernelGGL((k_valu_finish<FAM_POIS>), grid, block, 0, st, m, Gpart, ns, mode); break;
-    case FAM_HIER: hipLaunchKernelGGL((k_valu_finish<FAM_HIER>), grid, block, 0, st, m, Gpart, ns, mode); break;
-    default: return hipErrorInvalidValue;
+int valu_part_occupancy(bool fp64, int family, int pb, int W, size_t smem) {
+  switch (family) {
+    case FAM_GAUSS: return fp64 ? part_occupancy_fam<double, FAM_GAUSS>(pb, W, smem) : part_occupancy_fam<float, FAM_GAUSS>(pb, W, smem);
+    case FAM_LOGIT: return fp64 ? part_occupancy_fam<double, FAM_LOGIT>(pb, W, smem) : part_occupancy_fam<float, FAM_LOGIT>(pb, W, smem);
+    case FAM_POIS: return fp64 ? part_occupancy_fam<double, FAM_POIS>(pb, W, smem) : part_occupancy_fam<float, FAM_POIS>(pb, W, smem);
+    case FAM_HIER: return fp64 ? part_occupancy_fam<double, FAM_HIER>(pb, W, smem) : part_occupancy_fam<float, FAM_HIER>(pb, W, smem);
   }
+  return 0;
+}
+
+hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, const double* uscr, int ns, int mode,
+                              hipStream_t st) {
+  if (m.family != FAM_HIER) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_valu_finish, dim3(static_cast<unsigned>((m.d * m.C + 255) / 256)), dim3(256), 0, st, m, Gpart,
+                     uscr, ns, mode);
   return hipGetLastError();
 }
 

@@ -52,7 +52,8 @@ struct DevModel {
   const int32_t* test_ptr;    // [K+1]
   const int32_t* test_rows;   // [nnz]
   const int32_t* group_of;    // HIER [n]
-  const int32_t* wave_rows;   // VALU row partition [W+1]
+  const int32_t* wave_rows;   // VALU row partition [W+1] ([splits][W+1] on the row-split path)
+  const int32_t* gsplit;      // HIER row splits: first and last split spanning group g, [G][2]
   const double* minv;         // [d]
   const double* prior_prec;   // [d] 1/scale^2
   const double* fold_const;   // [K]
@@ -186,17 +187,54 @@ __device__ __forceinline__ double eta_row64(const DevModel& m, const double* q, 
   return e;
 }
 
+// Log density (fp64, with constants) of test slots [a0, a1) of chain c's
+// fold at q; the group location and scale are read once.
+template <int FAM>
+__device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, int a0, int a1) {
+  double mu = 0.0, tau = 0.0;
+  if (FAM == FAM_HIER) {
+    mu = q[m.p * m.C + c];
+    tau = exp(q[(m.p + 1) * m.C + c]);
+  }
+  double s = 0.0;
+  int t = a0;
+  // four rows at a time (their loads overlap); each row's arithmetic and the
+  // order of the sum over rows are those of the one-row loop below
+  for (; t + 4 <= a1; t += 4) {
+    int64_t i[4];
+    double e[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      i[u] = m.test_rows[t + u];
+      e[u] = 0.0;
+    }
+    for (int64_t j = 0; j < m.p; ++j) {
+      const double qj = q[j * m.C + c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e[u] += m.X64[i[u] * m.p + j] * qj;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (FAM == FAM_HIER) e[u] += mu + tau * q[(m.p + 2 + m.group_of[i[u]]) * m.C + c];
+      s += ell0_64<FAM>(m.y64[i[u]], e[u], m.inv_sigma2) + m.rowc[i[u]];
+    }
+  }
+  for (; t < a1; ++t) {
+    const int64_t i = m.test_rows[t];
+    const double* x = m.X64 + i * m.p;
+    double e = 0.0;
+    for (int64_t j = 0; j < m.p; ++j) e += x[j] * q[j * m.C + c];
+    if (FAM == FAM_HIER) e += mu + tau * q[(m.p + 2 + m.group_of[i]) * m.C + c];
+    s += ell0_64<FAM>(m.y64[i], e, m.inv_sigma2) + m.rowc[i];
+  }
+  return s;
+}
+
 // Joint log density of the fold's test rows at q (fp64, with constants).
 template <int FAM>
 __device__ double log_pred_fold(const DevModel& m, const double* q, int64_t c) {
   const int k = static_cast<int>(c / m.L);
-  double s = 0.0;
-  for (int t = m.test_ptr[k]; t < m.test_ptr[k + 1]; ++t) {
-    const int64_t i = m.test_rows[t];
-    const double eta = eta_row64(m, q, c, i);
-    s += ell0_64<FAM>(m.y64[i], eta, m.inv_sigma2) + m.rowc[i];
-  }
-  return s;
+  return log_pred_rows<FAM>(m, q, c, m.test_ptr[k], m.test_ptr[k + 1]);
 }
 
 // Prior: returns the non-constant part of log prior at q (constants are in fold_const).
@@ -220,6 +258,18 @@ __device__ __forceinline__ double prior_quad(const DevModel& m, const double* q,
   return v;
 }
 
+// Coordinate j's share of prior_quad at value t.
+__device__ __forceinline__ double prior_term(const DevModel& m, double t, int64_t j) {
+  if (m.family == FAM_HIER) {
+    if (j == m.p + 1) {
+      const double tau = exp(t);
+      return -0.5 * tau * tau + t;
+    }
+    return -0.5 * t * t;
+  }
+  return -0.5 * t * t * m.prior_prec[j];
+}
+
 __device__ __forceinline__ double prior_grad(const DevModel& m, double theta, int64_t j) {
   if (m.family == FAM_HIER) {
     if (j == m.p + 1) return -exp(2.0 * theta) + 1.0;
@@ -228,29 +278,34 @@ __device__ __forceinline__ double prior_grad(const DevModel& m, double theta, in
   return -theta * m.prior_prec[j];
 }
 
+// Momentum coordinates 2 jb and 2 jb + 1 of chain c at transition t (one
+// Philox block, Box-Muller), their half kick and drift; adds their kinetic
+// energy to k0.
+__device__ __forceinline__ void momentum_pair(const DevModel& m, int64_t c, int64_t t, int64_t jb, double& k0) {
+  const uint32_t gc = static_cast<uint32_t>(m.chain_offset + c);
+  const W4 w = philox4x32_10(W4{gc, static_cast<uint32_t>(t), TAG_MOMENTUM, static_cast<uint32_t>(jb)},
+                             m.key0, m.key1);
+  const double u1 = uniform01(w.x, w.y), u2 = uniform01(w.z, w.w);
+  const double r = sqrt(-2.0 * log(u1));
+  const double ang = 2.0 * M_PI * u2;
+  const double z[2] = {r * cos(ang), r * sin(ang)};
+  for (int h = 0; h < 2; ++h) {
+    const int64_t j = 2 * jb + h;
+    if (j >= m.d) break;
+    const double mi = m.minv[j];
+    double p = z[h] / sqrt(mi);
+    k0 += 0.5 * mi * p * p;
+    const int64_t o = j * m.C + c;
+    p += 0.5 * m.eps * m.g0[o];
+    m.pm[o] = p;
+    m.q1[o] = m.q0[o] + m.eps * mi * p;
+  }
+}
+
 // Momentum refresh, first half kick and first drift of one transition.
 __device__ __forceinline__ void momentum_and_first_drift(const DevModel& m, int64_t c, int64_t t) {
-  const uint32_t gc = static_cast<uint32_t>(m.chain_offset + c);
   double k0 = 0.0;
-  for (int64_t jb = 0; 2 * jb < m.d; ++jb) {
-    const W4 w = philox4x32_10(W4{gc, static_cast<uint32_t>(t), TAG_MOMENTUM, static_cast<uint32_t>(jb)},
-                               m.key0, m.key1);
-    const double u1 = uniform01(w.x, w.y), u2 = uniform01(w.z, w.w);
-    const double r = sqrt(-2.0 * log(u1));
-    const double ang = 2.0 * M_PI * u2;
-    const double z[2] = {r * cos(ang), r * sin(ang)};
-    for (int h = 0; h < 2; ++h) {
-      const int64_t j = 2 * jb + h;
-      if (j >= m.d) break;
-      const double mi = m.minv[j];
-      double p = z[h] / sqrt(mi);
-      k0 += 0.5 * mi * p * p;
-      const int64_t o = j * m.C + c;
-      p += 0.5 * m.eps * m.g0[o];
-      m.pm[o] = p;
-      m.q1[o] = m.q0[o] + m.eps * mi * p;
-    }
-  }
+  for (int64_t jb = 0; 2 * jb < m.d; ++jb) momentum_pair(m, c, t, jb, k0);
   m.h0[c] = -m.logp0[c] + k0;
 }
 
@@ -357,32 +412,24 @@ __device__ void accumulate_scores(const DevModel& m, int64_t c, int64_t t) {
   }
 }
 
-// Metropolis test at the end of a trajectory (q1, pm, logp1, g1), state
-// selection, log predictive at the new state and accumulation.
-template <int FAM>
-__device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
-  double k1 = 0.0;
-  for (int64_t j = 0; j < m.d; ++j) {
-    const double p = m.pm[j * m.C + c];
-    k1 += 0.5 * m.minv[j] * p * p;
-  }
+// Metropolis test of chain c at transition t, given the kinetic energy k1 at
+// the end of its trajectory (logp1 already set).
+__device__ __forceinline__ void metropolis(const DevModel& m, int64_t c, int64_t t, double k1, bool& accepted,
+                                           bool& divergent) {
   const double h1 = -m.logp1[c] + k1;
   const double log_ratio = m.h0[c] - h1;
   const uint32_t gc = static_cast<uint32_t>(m.chain_offset + c);
   const W4 w = philox4x32_10(W4{gc, static_cast<uint32_t>(t), TAG_ACCEPT, 0u}, m.key0, m.key1);
   const double u = uniform01(w.x, w.y);
   const bool finite = isfinite(log_ratio);
-  const bool accepted = finite && (log(u) < log_ratio);
-  const bool divergent = !finite || (-log_ratio > DIVERGENCE_THRESHOLD);
-  if (accepted) {
-    for (int64_t j = 0; j < m.d; ++j) {
-      const int64_t o = j * m.C + c;
-      m.q0[o] = m.q1[o];
-      m.g0[o] = m.g1[o];
-    }
-    m.logp0[c] = m.logp1[c];
-    m.s0[c] = log_pred_fold<FAM>(m, m.q0, c);
-  }
+  accepted = finite && (log(u) < log_ratio);
+  divergent = !finite || (-log_ratio > DIVERGENCE_THRESHOLD);
+}
+
+// Bookkeeping of transition t once the state (q0, s0) is selected: warm-up
+// sums, or the online accumulators, scores, stored draw and counters.
+template <int FAM>
+__device__ void record_draw(const DevModel& m, int64_t c, int64_t t, bool accepted, bool divergent) {
   if (t < m.n_warmup) {
     if (m.rhat_mode == 1) m.wsum[c] += m.s0[c];
   } else {
@@ -393,6 +440,29 @@ __device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
     m.nacc[c] += accepted ? 1 : 0;
     m.ndiv[c] += divergent ? 1 : 0;
   }
+}
+
+// Metropolis test at the end of a trajectory (q1, pm, logp1, g1), state
+// selection, log predictive at the new state and accumulation.
+template <int FAM>
+__device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
+  double k1 = 0.0;
+  for (int64_t j = 0; j < m.d; ++j) {
+    const double p = m.pm[j * m.C + c];
+    k1 += 0.5 * m.minv[j] * p * p;
+  }
+  bool accepted, divergent;
+  metropolis(m, c, t, k1, accepted, divergent);
+  if (accepted) {
+    for (int64_t j = 0; j < m.d; ++j) {
+      const int64_t o = j * m.C + c;
+      m.q0[o] = m.q1[o];
+      m.g0[o] = m.g1[o];
+    }
+    m.logp0[c] = m.logp1[c];
+    m.s0[c] = log_pred_fold<FAM>(m, m.q0, c);
+  }
+  record_draw<FAM>(m, c, t, accepted, divergent);
 }
 
 }  // namespace pcv
