@@ -82,20 +82,25 @@ def cpu_baseline(w, budget_s=15.0):
                       f"{dt:.1f} s, fp64 numpy"}
 
 
-def traffic_from_profiles(w, prec):
+def traffic_from_profiles(w, prec, kernel_name):
     """HBM bytes per launch of the gradient kernel from the committed counter
-    summary, or None if there is none or the kernel source changed since the
-    counters were taken."""
+    summary, or None if there is none or the kernel's sources (its .hip file
+    and the shared device header) changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{w.name}_{prec}.json")
-    src = os.path.join(ROOT, "paper_2310_07002_amd", "csrc", "k_mfma.hip")
-    if not os.path.exists(path) or not os.path.exists(src):
+    csrc = os.path.join(ROOT, "paper_2310_07002_amd", "csrc")
+    srcs = [os.path.join(csrc, "k_mfma.hip" if kernel_name.startswith("k_mfma") else "k_valu.hip"),
+            os.path.join(csrc, "pcv_internal.h")]
+    if not os.path.exists(path) or not all(os.path.exists(x) for x in srcs):
         return None
     try:
         with open(path) as f:
             t = json.load(f)
-        with open(src, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        hh = hashlib.sha256()
+        for x in srcs:
+            with open(x, "rb") as f:
+                hh.update(f.read())
+        h = hh.hexdigest()[:16]
         return t.get("bytes_per_launch") if t.get("kernel_source_sha256_16") == h else None
     except Exception:
         return None
@@ -188,7 +193,7 @@ def main():
     roofline = {"bound": "mfma" if prec.startswith("bf16") else "alu",
                 "kernel": k_name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": (achieved / peak) if achieved else None,
-                "traffic": traffic_from_profiles(w, prec),
+                "traffic": traffic_from_profiles(w, prec, k_name),
                 "alg_flops_per_launch": flops_per_launch, "mean_launch_ms": avg_s * 1e3,
                 "launches": k_n}
     if prec.startswith("bf16"):
