@@ -25,6 +25,7 @@ a Gaussian target, stationarity against the conjugate posterior
 from __future__ import annotations
 
 import dataclasses
+from typing import Optional
 
 import numpy as np
 
@@ -39,6 +40,7 @@ class ChainState:
     logp: np.ndarray     # [C]
     grad: np.ndarray     # [C, d]
     s: np.ndarray        # [C]  log predictive at q
+    alpha: Optional[np.ndarray] = None   # [C] acceptance statistic of the last transition
 
 
 def initial_state(w, roles, fold_of_chain, q0=None) -> ChainState:
@@ -89,10 +91,13 @@ def transition(w, st: ChainState, t: int, roles, fold_of_chain, chain_ids):
         divergent = (~finite) | (np.where(finite, -log_ratio, 0.0) > DIVERGENCE_THRESHOLD)
     a = accepted[:, None]
     q = np.where(a, q1, st.q)
+    # acceptance statistic min(1, e^(H0 - H1)); 0 for a non-finite energy
+    with np.errstate(over="ignore"):
+        alpha = np.where(finite, np.minimum(1.0, np.exp(np.where(finite, log_ratio, 0.0))), 0.0)
     new = ChainState(q=q,
                      logp=np.where(accepted, logp1, st.logp),
                      grad=np.where(a, g1, st.grad),
-                     s=st.s.copy())
+                     s=st.s.copy(), alpha=alpha)
     if np.any(accepted):
         s_new = model.log_pred(w, q, roles, fold_of_chain)
         new.s = np.where(accepted, s_new, st.s)

@@ -19,6 +19,8 @@ Stream layout (the HIP library implements the same layout independently):
   tag 1 = momentum refresh: block j gives coordinates 2j and 2j+1
   tag 2 = Metropolis accept: block 0, first two words
   tag 3 = block-shuffle benchmark
+  tag 4 = predictive draws of the test rows (DSS)
+  tag 5 = starting draw of each chain from the full-data draws
 Uniform from two words (w0, w1):
   u = ((w0 * 2^32 + w1) >> 12) * 2^-52 + 2^-53, strictly inside (0, 1), exact in fp64.
 Normal pair by Box-Muller from block words (w0,w1) -> u1 and (w2,w3) -> u2:
@@ -35,6 +37,7 @@ TAG_MOMENTUM = 1
 TAG_ACCEPT = 2
 TAG_SHUFFLE = 3
 TAG_PREDICT = 4      # predictive draws of the test rows (DSS)
+TAG_INIT = 5         # starting draw of each chain from the full-data draws (workflow Step 2)
 
 _M0 = np.uint64(0xD2511F53)
 _M1 = np.uint64(0xCD9E8D57)
@@ -129,3 +132,13 @@ def predictive_words(seed: int, chains, t: int, v: int):
     chains = np.asarray(chains, dtype=np.uint64)
     jj = np.arange(v, dtype=np.uint64)[None, :]
     return philox4x32_10((chains[:, None], np.uint64(t), np.uint64(TAG_PREDICT), jj), seed_key(seed))
+
+
+def init_draw_indices(seed: int, chains, n_draws: int) -> np.ndarray:
+    """Index of the full-data draw each chain starts from (workflow Step 2):
+    counter (chain, 0, TAG_INIT, 0), index = floor(u * n_draws) with u from the
+    first two words (clamped to n_draws - 1)."""
+    chains = np.asarray(chains, dtype=np.uint64)
+    w0, w1, _, _ = philox4x32_10((chains, np.uint64(0), np.uint64(TAG_INIT), np.uint64(0)), seed_key(seed))
+    u = uniform_from_words(w0, w1)
+    return np.minimum(np.floor(u * n_draws).astype(np.int64), n_draws - 1)

@@ -366,6 +366,28 @@ def fold_subset(w: Workload, k0: int, k1: int) -> Workload:
     return sub
 
 
+def full_data(w: Workload, L: int = 8, n_warmup: int = 1000) -> Workload:
+    """The full-data model of w (the workflow's Step 1): one fold whose rows
+    all train (fold id -1 everywhere, so no held-out rows and s = 0), L
+    chains started at the first L of w's starting positions, a unit inverse
+    mass and w's step size as the adaptation's starting point, and n_warmup
+    transitions counted as warm-up (no accumulation during adaptation)."""
+    sub = dataclasses.replace(w)
+    sub.name = w.name + "_full"
+    sub.K, sub.L = 1, L
+    sub.fold_kind = FOLDS_INDEX
+    sub.fold_index = np.full(w.n, -1, dtype=np.int32)
+    sub.intervals = None
+    sub.roles = None
+    sub.chain_offset = 0
+    sub.init_pos = np.array(w.init_pos[:L], dtype=np.float64)
+    sub.inv_mass = np.ones(w.d)
+    sub.n_warmup = n_warmup
+    sub.scores = 0
+    sub.store_draws = 0
+    return sub
+
+
 def drop_covariates(w: Workload, cols, zero: bool = False) -> Workload:
     """The same workload for the model without covariates `cols` (GLM
     families): the nested-model comparison of Section 2.3, model B missing
