@@ -180,7 +180,9 @@ typedef struct pcv_ctx_s* pcv_ctx;
  * X: as model->x_format says (n*p row-major fp64, or two bf16 planes); y: n
  * fp64.  Errors: PCV_ERR_INVALID_ARG (n, p, K <= 0;
  * L < 2; non-finite X, y or init_pos; y outside the family's support; a fold
- * with no test or no training row; step_size, inv_mass, sigma <= 0;
+ * with no training row; a fold with no test row when K > 1 (K = 1 without
+ * test rows is the full-data model, s = 0, which pcv_adapt tunes);
+ * step_size, inv_mass, sigma <= 0;
  * n_leapfrog < 1; batch settings < 1), PCV_ERR_UNSUPPORTED, PCV_ERR_NOMEM,
  * PCV_ERR_DEVICE.  *out is NULL on error. */
 pcv_status pcv_init(pcv_ctx* out, const pcv_model* model, const void* X, const double* y,
@@ -246,6 +248,42 @@ pcv_status pcv_posthoc(pcv_ctx ctx, pcv_posthoc_diag* out);
  * Errors: PCV_ERR_INVALID_ARG for a null output or different fold sets
  * (message on a); PCV_ERR_STATE when either run has no draw yet. */
 pcv_status pcv_compare(pcv_ctx a, pcv_ctx b, pcv_comparison* out);
+
+/* Full-data tuning by window adaptation (Section 3.1, efficient warm-up;
+ * workflow Step 1).  Meant for a context on the full data: one fold whose
+ * rows all train (PCV_FOLDS_INDEX, K = 1, every fold_index -1), L chains,
+ * and n_warmup >= n_adapt so no adaptation draw is accumulated.  Runs
+ * n_adapt transitions of ctx, eagerly:
+ *   step size  - after every transition, dual averaging (Hoffman and Gelman,
+ *                2014; gamma 0.05, t0 10, kappa 0.75) of the chains' mean
+ *                acceptance statistic min(1, e^(H0 - H1)) toward
+ *                target_accept in (0, 1);
+ *   inverse mass (diagonal) - at the end of each slow window, the
+ *                regularised variance n/(n+5) var + 1e-3 * 5/(n+5) of the
+ *                positions of all chains over the window (n = chains x
+ *                transitions), after which the dual averaging restarts.
+ * Windows (Stan's published schedule): a fast buffer of 75 transitions,
+ * slow windows of 25, 50, 100, ... (the last stretched to the final buffer),
+ * a final fast buffer of 50; 15% / rest / 10% of n_adapt when those do not
+ * fit.  On return the context runs with the adapted values (step size =
+ * exp of the averaged log step size) and its chains sit at the adapted
+ * positions; step_size (1 entry) and inv_mass (d entries) receive them when
+ * not NULL (caller-owned).  Synchronises every transition.
+ * Errors: PCV_ERR_INVALID_ARG for n_adapt < 1 or target_accept outside
+ * (0, 1); PCV_ERR_DEVICE on a failed copy (the context is then at an
+ * intermediate step size). */
+pcv_status pcv_adapt(pcv_ctx ctx, int64_t n_adapt, double target_accept, double* step_size, double* inv_mass);
+
+/* Starting positions drawn from full-data draws (workflow Step 2): chain c
+ * (global id chain_offset + c) starts at draw floor(u n_draws) of
+ * draws[n_draws][d] (row-major, host), u from Philox4x32-10 with key seed
+ * and counter (chain_offset + c, 0, 5, 0), first two words.  init_pos:
+ * C*d host doubles, chain-major (the layout of pcv_model.init_pos;
+ * caller-owned).  Pure host code: no context, no device.
+ * Errors: PCV_ERR_INVALID_ARG for null pointers, n_draws, d or C < 1, or
+ * chain ids beyond 32 bits. */
+pcv_status pcv_init_positions(const double* draws, int64_t n_draws, int64_t d, int64_t C, uint64_t seed,
+                              int64_t chain_offset, double* init_pos);
 
 void pcv_destroy(pcv_ctx ctx);
 const char* pcv_last_error(pcv_ctx ctx);

@@ -26,7 +26,7 @@ EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_el
             "pcv_destroy", "pcv_last_error", "pcv_status_str",
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
             "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
-            "pcv_timing_enable", "pcv_timing_read"]
+            "pcv_adapt", "pcv_init_positions", "pcv_timing_enable", "pcv_timing_read"]
 
 
 class PcvError(RuntimeError):
@@ -125,6 +125,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_load": ([P, ctypes.c_char_p], I32),
         "pcv_philox": ([U64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, I64,
                         ctypes.POINTER(ctypes.c_uint32)], I32),
+        "pcv_adapt": ([P, I64, D, dp, dp], I32),
+        "pcv_init_positions": ([dp, I64, I64, I64, U64, I64, dp], I32),
         "pcv_timing_enable": ([P, I32], I32),
         "pcv_timing_read": ([P, dp, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_char_p), I32], I32),
     }
@@ -148,6 +150,19 @@ def _dev(t) -> ctypes.c_void_p:
     if not t.is_cuda or t.dtype != __import__("torch").float64 or not t.is_contiguous():
         raise ValueError("device arrays must be contiguous float64 tensors on the GPU")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def init_positions(draws: np.ndarray, C: int, seed: int, chain_offset: int = 0) -> np.ndarray:
+    """Starting positions [C, d] drawn from full-data draws [n_draws, d]
+    (pcv_init_positions)."""
+    lib = load_library()
+    draws = np.ascontiguousarray(draws, dtype=np.float64)
+    n_draws, d = draws.shape
+    out = np.zeros((C, d))
+    st = lib.pcv_init_positions(_dptr(draws), n_draws, d, C, seed, chain_offset, _dptr(out))
+    if st != PCV_OK:
+        raise PcvError(st, "pcv_init_positions failed")
+    return out
 
 
 def pcv_philox(seed: int, c0: int, c1: int, c2: int, c3: int, n: int) -> np.ndarray:
@@ -401,6 +416,16 @@ class PCV:
         self._check(self._lib.pcv_autotune(self._ctx, os.fsencode(cache_path) if cache_path else None,
                                            ctypes.byref(cfg), ctypes.byref(ms)), "pcv_autotune")
         return {"config": cfg.value, "ms": ms.value}
+
+    def adapt(self, n_adapt: int, target_accept: float = 0.8) -> dict:
+        """Window adaptation of the step size and diagonal inverse mass over
+        n_adapt transitions of this (full-data) context (pcv_adapt); the
+        context keeps the adapted values."""
+        eps = ctypes.c_double()
+        minv = np.zeros(self.d)
+        self._check(self._lib.pcv_adapt(self._ctx, n_adapt, target_accept, ctypes.byref(eps), _dptr(minv)),
+                    "pcv_adapt")
+        return {"step_size": eps.value, "inv_mass": minv}
 
     def save(self, path: str):
         """Checkpoint the run (state, accumulators, transition count) to `path`."""

@@ -547,7 +547,9 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown fold encoding");
   }
   for (int k = 0; k < K; ++k) {
-    if (test_ptr[k + 1] == test_ptr[k]) return fail(ctx, PCV_ERR_INVALID_ARG, "a fold has no test row");
+    // a single fold without test rows is the full-data model (s = 0), the
+    // context that pcv_adapt tunes
+    if (test_ptr[k + 1] == test_ptr[k] && K > 1) return fail(ctx, PCV_ERR_INVALID_ARG, "a fold has no test row");
     if (train_cnt[k] <= 0) return fail(ctx, PCV_ERR_INVALID_ARG, "a fold has no training row");
   }
 
@@ -722,6 +724,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   TRY(dalloc(ctx, &m.wsum, C));
   TRY(dalloc(ctx, &m.center, static_cast<size_t>(K)));
   TRY(dalloc(ctx, &m.t_dev, 1));
+  TRY(dalloc(ctx, &m.acc_stat, C));
   TRY(dalloc(ctx, &ctx->fold_buf, 6 * static_cast<size_t>(K)));
   TRY(dalloc(ctx, &ctx->dscal, 8));
   TRY(dalloc(ctx, &ctx->Vpart, C));
@@ -1689,6 +1692,127 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
     if (!replaced) cache.push_back({key, best, best_ms});
     if (!cache_write(cache_path, cache))
       return fail(ctx, PCV_ERR_INVALID_ARG, std::string("cannot write the tuning cache ") + cache_path);
+  }
+  return PCV_OK;
+}
+
+// ---- full-data tuning (Section 3.1; workflow Steps 1-2) ----------------------
+
+pcv_status pcv_adapt(pcv_ctx ctx, int64_t n_adapt, double target_accept, double* step_size, double* inv_mass) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (n_adapt < 1) return fail(ctx, PCV_ERR_INVALID_ARG, "n_adapt must be >= 1");
+  if (!(target_accept > 0.0 && target_accept < 1.0))
+    return fail(ctx, PCV_ERR_INVALID_ARG, "target_accept must lie in (0, 1)");
+  DevModel& m = ctx->m;
+  const int64_t d = m.d, C = m.C;
+  // Schedule: initial fast buffer, doubling slow windows (the last stretched
+  // to the final buffer), final fast buffer; 75 / 25 / 50, or 15% / rest / 10%
+  // of n_adapt when those do not fit.
+  int64_t init = 75, term = 50, win = 25;
+  if (init + win + term > n_adapt) {
+    init = static_cast<int64_t>(0.15 * static_cast<double>(n_adapt));
+    term = static_cast<int64_t>(0.1 * static_cast<double>(n_adapt));
+    win = n_adapt - init - term;
+  }
+  std::vector<int64_t> ends;
+  if (win > 0) {
+    const int64_t last = n_adapt - term;
+    for (int64_t start = init, size = win; start < last; size *= 2) {
+      int64_t end = start + size;
+      if (end + 2 * size > last) end = last;
+      ends.push_back(end);
+      start = end;
+    }
+  }
+  const int64_t slow_lo = init, slow_hi = ends.empty() ? 0 : ends.back();
+  // dual averaging of log eps toward the target acceptance statistic
+  const double gamma = 0.05, t0 = 10.0, kappa = 0.75;
+  double log_eps = std::log(m.eps), mu = std::log(10.0 * m.eps), hbar = 0.0, log_epsbar = 0.0;
+  int64_t mda = 0;
+  std::vector<double> alpha(static_cast<size_t>(C)), q(static_cast<size_t>(d * C));
+  std::vector<double> mean(static_cast<size_t>(d), 0.0), m2(static_cast<size_t>(d), 0.0), minv(static_cast<size_t>(d));
+  int64_t nwin = 0;
+  CK(hipMemcpy(minv.data(), m.minv, sizeof(double) * d, hipMemcpyDeviceToHost));
+  const bool graphs = ctx->graphs;
+  ctx->graphs = false;   // the step size changes every transition: eager launches
+  drop_graph(ctx);
+  pcv_status st = PCV_OK;
+  size_t next_end = 0;
+  for (int64_t t = 0; t < n_adapt && st == PCV_OK; ++t) {
+    m.eps = std::exp(log_eps);
+    st = pcv_step(ctx, 1);
+    if (st != PCV_OK) break;
+    if (hipMemcpyAsync(alpha.data(), m.acc_stat, sizeof(double) * C, hipMemcpyDeviceToHost, ctx->st) != hipSuccess ||
+        hipStreamSynchronize(ctx->st) != hipSuccess) {
+      st = fail(ctx, PCV_ERR_DEVICE, "reading the acceptance statistics failed");
+      break;
+    }
+    double a = 0.0;
+    for (int64_t c = 0; c < C; ++c) a += alpha[c];
+    a /= static_cast<double>(C);
+    mda += 1;
+    const double w = 1.0 / (static_cast<double>(mda) + t0);
+    hbar = (1.0 - w) * hbar + w * (target_accept - a);
+    log_eps = mu - std::sqrt(static_cast<double>(mda)) / gamma * hbar;
+    const double eta = std::pow(static_cast<double>(mda), -kappa);
+    log_epsbar = eta * log_eps + (1.0 - eta) * log_epsbar;
+    if (t >= slow_lo && t < slow_hi) {
+      // positions of every chain feed a per-coordinate Welford variance
+      if (hipMemcpy(q.data(), m.q0, sizeof(double) * d * C, hipMemcpyDeviceToHost) != hipSuccess) {
+        st = fail(ctx, PCV_ERR_DEVICE, "reading the positions failed");
+        break;
+      }
+      for (int64_t c = 0; c < C; ++c) {
+        nwin += 1;
+        for (int64_t j = 0; j < d; ++j) {
+          const double x = q[j * C + c];
+          const double dx = x - mean[j];
+          mean[j] += dx / static_cast<double>(nwin);
+          m2[j] += dx * (x - mean[j]);
+        }
+      }
+    }
+    if (next_end < ends.size() && t + 1 == ends[next_end]) {
+      ++next_end;
+      const double nn = static_cast<double>(nwin);
+      for (int64_t j = 0; j < d; ++j)
+        minv[j] = nn / (nn + 5.0) * (nwin > 1 ? m2[j] / (nn - 1.0) : 0.0) + 1e-3 * 5.0 / (nn + 5.0);
+      if (hipMemcpy(const_cast<double*>(m.minv), minv.data(), sizeof(double) * d, hipMemcpyHostToDevice) !=
+          hipSuccess) {
+        st = fail(ctx, PCV_ERR_DEVICE, "writing the inverse mass failed");
+        break;
+      }
+      std::fill(mean.begin(), mean.end(), 0.0);
+      std::fill(m2.begin(), m2.end(), 0.0);
+      nwin = 0;
+      log_eps = std::log(std::exp(log_eps));     // restart the dual averaging from the current eps
+      mu = std::log(10.0 * std::exp(log_eps));
+      hbar = 0.0;
+      log_epsbar = 0.0;
+      mda = 0;
+    }
+  }
+  ctx->graphs = graphs;
+  if (st != PCV_OK) return st;
+  m.eps = std::exp(log_epsbar);
+  drop_graph(ctx);   // a captured transition holds the old step size
+  if (step_size) *step_size = m.eps;
+  if (inv_mass) std::memcpy(inv_mass, minv.data(), sizeof(double) * d);
+  return PCV_OK;
+}
+
+pcv_status pcv_init_positions(const double* draws, int64_t n_draws, int64_t d, int64_t C, uint64_t seed,
+                              int64_t chain_offset, double* init_pos) {
+  if (!draws || !init_pos || n_draws < 1 || d < 1 || C < 1 || chain_offset < 0 ||
+      chain_offset + C > 0xFFFFFFFFLL)
+    return PCV_ERR_INVALID_ARG;
+  const uint32_t k0 = static_cast<uint32_t>(seed & 0xFFFFFFFFu), k1 = static_cast<uint32_t>(seed >> 32);
+  for (int64_t c = 0; c < C; ++c) {
+    const W4 w = philox4x32_10(W4{static_cast<uint32_t>(chain_offset + c), 0u, TAG_INIT, 0u}, k0, k1);
+    const double u = uniform01(w.x, w.y);
+    int64_t idx = static_cast<int64_t>(std::floor(u * static_cast<double>(n_draws)));
+    if (idx > n_draws - 1) idx = n_draws - 1;
+    std::memcpy(init_pos + c * d, draws + idx * d, sizeof(double) * d);
   }
   return PCV_OK;
 }

@@ -16,6 +16,7 @@ constexpr uint32_t TAG_MOMENTUM = 1;
 constexpr uint32_t TAG_ACCEPT = 2;
 constexpr uint32_t TAG_SHUFFLE = 3;
 constexpr uint32_t TAG_PREDICT = 4;   // predictive draws of the test rows (DSS)
+constexpr uint32_t TAG_INIT = 5;      // starting draw of a chain from the full-data draws
 constexpr double DIVERGENCE_THRESHOLD = 1000.0;
 constexpr int MAX_BLOCKS = 64;
 
@@ -83,6 +84,9 @@ struct DevModel {
   // device-side transition counter (read when a kernel is given t < 0, so
   // one captured graph of a transition can be replayed)
   int64_t* t_dev;
+  // [C] acceptance statistic min(1, e^(H0 - H1)) of the last transition (0
+  // for a non-finite energy); read by the window adaptation
+  double* acc_stat;
 };
 
 // ----------------------------------------------------------------------------
@@ -92,23 +96,25 @@ struct W4 {
   uint32_t x, y, z, w;
 };
 
-// Philox4x32 with ten rounds (Salmon et al., SC'11).
-__device__ __forceinline__ W4 philox4x32_10(W4 c, uint32_t k0, uint32_t k1) {
+// Philox4x32 with ten rounds (Salmon et al., SC'11); also used on the host.
+__host__ __device__ __forceinline__ W4 philox4x32_10(W4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c.x;
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c.z;
+    const uint32_t lo0 = static_cast<uint32_t>(p0), hi0 = static_cast<uint32_t>(p0 >> 32);
+    const uint32_t lo1 = static_cast<uint32_t>(p1), hi1 = static_cast<uint32_t>(p1 >> 32);
     c = W4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
   }
   return c;
 }
 
 // Two 32-bit words -> double strictly inside (0,1): top 52 bits, centred in their cell.
-__device__ __forceinline__ double uniform01(uint32_t w0, uint32_t w1) {
+__host__ __device__ __forceinline__ double uniform01(uint32_t w0, uint32_t w1) {
   const uint64_t b = (static_cast<uint64_t>(w0) << 32) | w1;
   return static_cast<double>(b >> 12) * 0x1p-52 + 0x1p-53;
 }
@@ -424,6 +430,7 @@ __device__ __forceinline__ void metropolis(const DevModel& m, int64_t c, int64_t
   const bool finite = isfinite(log_ratio);
   accepted = finite && (log(u) < log_ratio);
   divergent = !finite || (-log_ratio > DIVERGENCE_THRESHOLD);
+  if (m.acc_stat) m.acc_stat[c] = finite ? (log_ratio >= 0.0 ? 1.0 : exp(log_ratio)) : 0.0;
 }
 
 // Bookkeeping of transition t once the state (q0, s0) is selected: warm-up

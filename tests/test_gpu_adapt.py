@@ -1,0 +1,115 @@
+"""Full-data window adaptation and chain starts on the device against the
+oracle (needs an MI355X).  fp64 paths replay the oracle transition for
+transition over a short adaptation (to rounding); long adaptations are
+checked against the exact posterior scale; the workflow test checks the
+cross-validation that follows."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import adapt, closed_form, folds
+from paper_2310_07002_amd import binding, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("name", ["c1", "c3"])
+def test_adapt_replays_the_oracle_over_a_short_horizon(dev, name):
+    """c1: fused VALU path; c3 (4996 rows, 8 chains): row-split path.
+    16 transitions: buffers of 2 and 1 around one slow window of 13, so the
+    schedule, the dual averaging, the window variance and the restart all
+    run.  The horizon is short on purpose: in the early phase the dual
+    averaging's feedback (step size -> acceptance -> step size) multiplies a
+    rounding difference by about two per transition, so two correct
+    implementations that add in different orders drift apart after a few
+    dozen transitions (the long runs are checked statistically below)."""
+    n_adapt = 16
+    f = W.full_data(W.make(name), L=8, n_warmup=n_adapt + 10)
+    _say(f"[adapt] {name} n_adapt={n_adapt}")
+    s = binding.PCV.from_workload(f, precision=W.PREC_FP64)
+    r = s.adapt(n_adapt, 0.8)
+    th, _, _ = s.get_state()
+    fa, st, eps, acc = adapt.adapt(f, n_adapt, 0.8)
+    _say(f"[adapt] {name}: eps {r['step_size']:.9g} (oracle {fa.step_size:.9g})")
+    assert adapt.slow_window_ends(n_adapt) == [15]
+    assert r["step_size"] == pytest.approx(fa.step_size, rel=1e-7)
+    np.testing.assert_allclose(r["inv_mass"], fa.inv_mass, rtol=1e-7)
+    np.testing.assert_allclose(th, st.q, rtol=1e-7, atol=1e-12)
+    # the context keeps the adapted tuning: further transitions still replay
+    s.step(3)
+    th2, _, _ = s.get_state()
+    from oracle import hmc
+    roles = folds.roles_of(fa)
+    for t in range(n_adapt, n_adapt + 3):
+        st, _, _ = hmc.transition(fa, st, t, roles, np.zeros(fa.C, dtype=np.int64), np.arange(fa.C))
+    np.testing.assert_allclose(th2, st.q, rtol=1e-7, atol=1e-12)
+    s.close()
+
+
+def test_long_adaptation_finds_the_posterior_scale(dev):
+    """1000 transitions on the conjugate Gaussian's full data: the adapted
+    inverse mass estimates the exact posterior variances (within 30%, as the
+    oracle's own pin), and the step size lies within 25% of the oracle's."""
+    w = W.make("c1")
+    f = W.full_data(w, L=8, n_warmup=2000)
+    s = binding.PCV.from_workload(f, precision=W.PREC_FP64)
+    r = s.adapt(1000, 0.8)
+    s.close()
+    _, V, _ = closed_form.fold_posterior(w.X, w.y, w.sigma, w.prior_scale, np.ones(w.n, dtype=bool))
+    ratio = r["inv_mass"] / np.diag(V)
+    fa, _, _, _ = adapt.adapt(f, 1000, 0.8)
+    _say(f"[adapt] long: eps {r['step_size']:.4f} (oracle {fa.step_size:.4f}); Minv / var {ratio}")
+    assert (np.abs(ratio - 1.0) < 0.3).all()
+    assert abs(r["step_size"] / fa.step_size - 1.0) < 0.25
+
+
+def test_init_positions_match_the_oracle(dev):
+    rng = np.random.default_rng(3)
+    draws = rng.standard_normal((137, 6))
+    for seed, off, C in [(0, 0, 1), (20231007, 0, 400), (2 ** 63 + 5, 1000, 64)]:
+        np.testing.assert_array_equal(binding.init_positions(draws, C, seed, off),
+                                      adapt.init_positions(draws, C, seed, off))
+
+
+def test_workflow_full_data_tuning_then_cv(dev):
+    """Steps 1-2 on the conjugate Gaussian: adapt on the full data, take
+    full-data draws, start every LOO chain at one of them with the adapted
+    step size and inverse mass, discard a short warm-up, and sample: the
+    elpd lies within 4 MCSE of the exact value."""
+    w = W.make("c1")
+    f = W.full_data(w, L=8, n_warmup=2000)
+    s = binding.PCV.from_workload(f, precision=W.PREC_FP64)
+    r = s.adapt(1000, 0.8)
+    draws = []
+    for _ in range(100):
+        s.step(2)
+        draws.append(s.get_state()[0].copy())
+    s.close()
+    draws = np.concatenate(draws, axis=0)
+    init = binding.init_positions(draws, w.C, w.seed)
+    np.testing.assert_array_equal(init, adapt.init_positions(draws, w.C, w.seed))
+    cv = dataclasses.replace(w, step_size=r["step_size"], inv_mass=r["inv_mass"], init_pos=init,
+                             n_warmup=50, n_samples=1000)
+    c = binding.PCV.from_workload(cv, precision=W.PREC_FP64)
+    c.step(cv.n_warmup + cv.n_samples)
+    e = c.elpd()
+    exact = 0.0
+    for k in range(w.K):
+        test = w.fold_index == k
+        exact += closed_form.fold_exact(w.X, w.y, w.sigma, w.prior_scale, ~test, test)["elpd"]
+    _say(f"[workflow] eps {r['step_size']:.4f}; elpd {e['elpd']:.4f} +- {e['mcse']:.4f}, exact {exact:.4f}")
+    assert abs(e["elpd"] - exact) < 4 * e["mcse"]
+    c.close()
