@@ -281,6 +281,64 @@ def test_bf16_run_tracks_oracle_c5(dev, prec):
     assert err[same].max() < 1e-5
 
 
+def _regrouped(w):
+    """The hierarchical design of w with its groups relabelled so that row 0
+    is a group of its own, every original group g becomes group 2g+1, and
+    the even groups in between (and one past the end) have no rows: only
+    their prior informs them.  Rows stay sorted by group."""
+    g = 2 * w.group_of.astype(np.int64) + 1
+    g[0] = 0
+    G2 = 2 * w.n_groups + 2
+    p = w.p
+    z_of = np.zeros(G2, dtype=np.int64) - 1          # original group behind each new group
+    z_of[2 * np.arange(w.n_groups) + 1] = np.arange(w.n_groups)
+    z_of[0] = w.group_of[0]
+    def expand(a, fill):                              # [..., p + 2 + G] -> [..., p + 2 + G2]
+        out = np.full(a.shape[:-1] + (p + 2 + G2,), fill, dtype=np.float64)
+        out[..., :p + 2] = a[..., :p + 2]
+        has = z_of >= 0
+        out[..., p + 2:][..., has] = a[..., p + 2 + z_of[has]]
+        return out
+    return dataclasses.replace(w, group_of=g.astype(np.int32), n_groups=G2,
+                               init_pos=expand(w.init_pos, 0.0), inv_mass=expand(w.inv_mass, 1.0),
+                               prior_scale=expand(w.prior_scale, 1.0),
+                               truth=expand(w.truth, 0.0) if w.truth is not None else None)
+
+
+@pytest.mark.parametrize("n_keep", [22, 12])
+def test_hier_empty_and_single_row_groups(dev, n_keep):
+    """Hierarchical groups with no rows and with one row, and groups that
+    straddle waves and row splits, on the rows of the first n_keep groups of
+    the LOGO workload: 22 groups (over 2048 rows, 64 chains) run on the
+    row-split path, 12 groups (under 2048 rows) on the fused path.  fp64,
+    against the oracle."""
+    base = W.make("c2")
+    rows = int(np.searchsorted(base.group_of, n_keep))
+    base = dataclasses.replace(base, X=base.X[:rows], y=base.y[:rows], fold_index=base.fold_index[:rows],
+                               group_of=base.group_of[:rows], n_groups=n_keep, K=n_keep,
+                               init_pos=base.init_pos[:n_keep * base.L, :base.p + 2 + n_keep],
+                               inv_mass=base.inv_mass[:base.p + 2 + n_keep],
+                               prior_scale=base.prior_scale[:base.p + 2 + n_keep],
+                               truth=base.truth[:base.p + 2 + n_keep])
+    assert (rows >= 2048) == (n_keep == 22)
+    w = dataclasses.replace(_regrouped(W.fold_subset(base, 0, 4)), precision=W.PREC_FP64, n_warmup=2)
+    _say(f"[hier groups] n={w.n} groups={w.n_groups} C={w.C}")
+    theta = _theta_near_init(w, seed=11)
+    lp_o, g_o = _oracle_eval(w, theta)
+    s = binding.PCV.from_workload(w, precision=W.PREC_FP64)
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    rel_v = np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)
+    rel_g = _normwise(g.cpu().numpy(), g_o)
+    _say(f"    logp rel max {rel_v.max():.2e}  grad normwise max {rel_g.max():.2e}")
+    assert rel_v.max() < 1e-12
+    assert rel_g.max() < 1e-12
+    # three whole transitions replay the oracle
+    run, s2 = _replay(w, 3, dev, prec=W.PREC_FP64)
+    th, _, sv = s2.get_state()
+    np.testing.assert_allclose(th, run.state.q, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(sv, run.state.s, rtol=1e-10, atol=1e-12)
+
+
 def test_hier_fp32_run_tracks_oracle(dev):
     w = dataclasses.replace(W.make("c2"), n_warmup=2)
     w = W.fold_subset(w, 0, 10)
