@@ -132,6 +132,16 @@ typedef struct pcv_model {
   int32_t scores;              /* PCV_SCORE_* mask (0 = LogS only)                   */
   int64_t store_draws;         /* keep the first store_draws post-warm-up draws of s
                                   of every chain on the device (Algorithm 1); 0 = none */
+  /* Several nested models in one launch (Appendix B, parallel model
+   * evaluation): model m uses covariate j iff model_mask[m*p + j] = 1; a
+   * masked beta_j stays a parameter that the likelihood and the predictive
+   * ignore (x_nj beta_j enters as 0) and only its prior informs.  The run
+   * then holds M*K posteriors, model-major: chain c = (m*K + k)*L + l is chain
+   * l of fold k under model m, so C = M*K*L and init_pos has M*K*L rows; the
+   * per-fold arrays of the diagnostics have M*K entries in the same order.
+   * GLM families; not with scores or the plain fp64 path. */
+  int32_t n_models;            /* M (0 or 1: one model, model_mask ignored)          */
+  const uint8_t* model_mask;   /* M*p entries, 0 or 1                               */
 } pcv_model;
 
 typedef struct pcv_diag {
@@ -143,8 +153,8 @@ typedef struct pcv_diag {
   int64_t n_divergent;    /* post-warm-up divergent transitions                    */
   int64_t n_draws;        /* post-warm-up draws per chain                          */
   int64_t n_iter;         /* transitions run so far (warm-up included)             */
-  double* rhat_fold;      /* optional, K entries, caller-owned                      */
-  double* ess_fold;       /* optional, K entries, caller-owned                      */
+  double* rhat_fold;      /* optional, K entries (M*K with several models), caller-owned */
+  double* ess_fold;       /* optional, K entries (M*K with several models), caller-owned */
 } pcv_diag;
 
 /* Comparison of two models on the same folds (Sections 2.3 and 4.1). */
@@ -206,8 +216,17 @@ pcv_status pcv_diagnostics(pcv_ctx ctx, pcv_diag* out);
 
 /* LogS cross-validation estimate (eq cv-score) and its Monte Carlo standard
  * error (eq mc-var), in total and per fold (K entries each, optional).
+ * With several models the totals run over all M*K posteriors and the
+ * per-fold arrays have M*K entries; pcv_elpd_model gives one model's.
  * Synchronises.  PCV_ERR_STATE if there is no post-warm-up draw. */
 pcv_status pcv_elpd(pcv_ctx ctx, double* elpd, double* mcse, double* elpd_fold, double* mcse_fold);
+
+/* The same for model `model` of a multi-model run (0 <= model < M; model 0
+ * of a one-model run): elpd and mcse over its K folds, per-fold arrays of K
+ * entries (optional).  Errors: PCV_ERR_INVALID_ARG for a model out of
+ * range; PCV_ERR_STATE without post-warm-up draws. */
+pcv_status pcv_elpd_model(pcv_ctx ctx, int32_t model, double* elpd, double* mcse, double* elpd_fold,
+                          double* mcse_fold);
 
 /* Block-shuffle benchmark of Rhat_max (Section 4.2, Fig. 4; last loop of
  * Algorithm A2): R replicates, each rebuilding every chain from D blocks
@@ -244,10 +263,18 @@ pcv_status pcv_posthoc(pcv_ctx ctx, pcv_posthoc_diag* out);
 /* Pairwise model comparison from two runs on the same folds (same fold
  * encoding and arrays, checked by fingerprint): context a holds model A,
  * context b model B, for instance nested designs that differ by a covariate
- * (Section 2.3).  Both need post-warm-up draws.  Synchronises both streams.
+ * (Section 2.3).  Both need post-warm-up draws and one model each
+ * (pcv_compare_models compares the models of one run).  Synchronises both
+ * streams.
  * Errors: PCV_ERR_INVALID_ARG for a null output or different fold sets
  * (message on a); PCV_ERR_STATE when either run has no draw yet. */
 pcv_status pcv_compare(pcv_ctx a, pcv_ctx b, pcv_comparison* out);
+
+/* The same comparison between models a and b of one multi-model run (both
+ * models in one launch, Appendix B): their posteriors share the folds by
+ * construction.  Errors: PCV_ERR_INVALID_ARG for models out of range or a
+ * null output; PCV_ERR_STATE without post-warm-up draws. */
+pcv_status pcv_compare_models(pcv_ctx ctx, int32_t a, int32_t b, pcv_comparison* out);
 
 /* Full-data tuning by window adaptation (Section 3.1, efficient warm-up;
  * workflow Step 1).  Meant for a context on the full data: one fold whose

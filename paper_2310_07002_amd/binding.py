@@ -26,7 +26,8 @@ EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_el
             "pcv_destroy", "pcv_last_error", "pcv_status_str",
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
             "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
-            "pcv_adapt", "pcv_init_positions", "pcv_timing_enable", "pcv_timing_read"]
+            "pcv_adapt", "pcv_init_positions", "pcv_elpd_model", "pcv_compare_models",
+            "pcv_timing_enable", "pcv_timing_read"]
 
 
 class PcvError(RuntimeError):
@@ -55,7 +56,8 @@ class pcv_model(ctypes.Structure):
                 ("batches_per_block", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("chain_offset", ctypes.c_int64),
                 ("x_format", ctypes.c_int32), ("rhat_mode", ctypes.c_int32),
-                ("scores", ctypes.c_int32), ("store_draws", ctypes.c_int64)]
+                ("scores", ctypes.c_int32), ("store_draws", ctypes.c_int64),
+                ("n_models", ctypes.c_int32), ("model_mask", ctypes.POINTER(ctypes.c_uint8))]
 
 X_FP64, X_BF16_HILO = 0, 1
 RHAT_WELFORD, RHAT_SHIFTED_SUMS = 0, 1
@@ -126,6 +128,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_philox": ([U64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, I64,
                         ctypes.POINTER(ctypes.c_uint32)], I32),
         "pcv_adapt": ([P, I64, D, dp, dp], I32),
+        "pcv_elpd_model": ([P, I32, dp, dp, dp, dp], I32),
+        "pcv_compare_models": ([P, I32, I32, ctypes.POINTER(pcv_comparison)], I32),
         "pcv_init_positions": ([dp, I64, I64, I64, U64, I64, dp], I32),
         "pcv_timing_enable": ([P, I32], I32),
         "pcv_timing_read": ([P, dp, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_char_p), I32], I32),
@@ -183,9 +187,11 @@ class PCV:
                  n_leapfrog: int, inv_mass, init_pos, n_warmup: int, batch_size: int,
                  batches_per_block: int, n_blocks: int, seed: int, chain_offset: int = 0,
                  x_format: int = X_FP64, rhat_mode: int = RHAT_WELFORD, scores: int = 0,
-                 store_draws: int = 0, stream=None):
+                 store_draws: int = 0, n_models: int = 1, model_mask=None, stream=None):
         """X: [n, p] float64, or with x_format=X_BF16_HILO a [2, n, p] uint16
-        array of bf16 bit patterns (hi plane, lo plane)."""
+        array of bf16 bit patterns (hi plane, lo plane).  n_models > 1 with
+        model_mask [n_models, p] (0/1): several nested models in one launch,
+        n_models * K * L chains, model-major."""
         self._lib = load_library()
         if x_format == X_BF16_HILO:
             X = np.ascontiguousarray(X, dtype=np.uint16)
@@ -196,7 +202,8 @@ class PCV:
             n, p = X.shape
         y = np.ascontiguousarray(y, dtype=np.float64)
         self.n, self.p, self.K, self.L = n, p, int(K), int(L)
-        self.C = self.K * self.L
+        self.M = max(1, int(n_models))
+        self.C = self.M * self.K * self.L
         self._scores = int(scores)
         self.d = p + 2 + n_groups if group_of is not None else p
         keep = []
@@ -215,6 +222,7 @@ class PCV:
         fi = arr(fold_index, np.int32)
         iv = arr(intervals, np.int64)
         rl = arr(roles, np.int8)
+        mm = arr(model_mask, np.uint8) if self.M > 1 else None
         m = pcv_model()
         m.family, m.precision = family, precision
         m.n, m.p, m.K, m.L = n, p, K, L
@@ -230,6 +238,8 @@ class PCV:
         m.seed, m.chain_offset = seed, chain_offset
         m.x_format, m.rhat_mode, m.scores = x_format, rhat_mode, scores
         m.store_draws = store_draws
+        m.n_models = self.M
+        m.model_mask = mm.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if mm is not None else None
         f = pcv_folds()
         f.kind = fold_kind
         f.fold_index = fi.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if fi is not None else None
@@ -262,7 +272,8 @@ class PCV:
                    n_leapfrog=w.n_leapfrog, inv_mass=w.inv_mass, init_pos=w.init_pos,
                    n_warmup=w.n_warmup, batch_size=w.batch_size,
                    batches_per_block=w.batches_per_block, n_blocks=w.n_blocks, seed=w.seed,
-                   chain_offset=w.chain_offset, stream=stream)
+                   chain_offset=w.chain_offset, n_models=getattr(w, "n_models", 1),
+                   model_mask=getattr(w, "model_mask", None), stream=stream)
 
     # -- helpers ---------------------------------------------------------------
     def _check(self, st: int, what: str):
@@ -290,8 +301,8 @@ class PCV:
         self._check(self._lib.pcv_step(self._ctx, int(n_iter)), "pcv_step")
 
     def diagnostics(self) -> dict:
-        rf = np.zeros(self.K)
-        ef = np.zeros(self.K)
+        rf = np.zeros(self.M * self.K)
+        ef = np.zeros(self.M * self.K)
         d = pcv_diag()
         d.rhat_fold = _dptr(rf)
         d.ess_fold = _dptr(ef)
@@ -303,18 +314,37 @@ class PCV:
     def elpd(self) -> dict:
         e = ctypes.c_double()
         s = ctypes.c_double()
-        ef = np.zeros(self.K)
-        sf = np.zeros(self.K)
+        ef = np.zeros(self.M * self.K)
+        sf = np.zeros(self.M * self.K)
         self._check(self._lib.pcv_elpd(self._ctx, ctypes.byref(e), ctypes.byref(s), _dptr(ef), _dptr(sf)),
                     "pcv_elpd")
         return {"elpd": e.value, "mcse": s.value, "elpd_fold": ef, "mcse_fold": sf}
 
+    def elpd_model(self, model: int) -> dict:
+        """elpd and MCSE of one model of a multi-model run, in total and per fold."""
+        e = ctypes.c_double()
+        s = ctypes.c_double()
+        ef = np.zeros(self.K)
+        sf = np.zeros(self.K)
+        self._check(self._lib.pcv_elpd_model(self._ctx, model, ctypes.byref(e), ctypes.byref(s), _dptr(ef),
+                                             _dptr(sf)), "pcv_elpd_model")
+        return {"elpd": e.value, "mcse": s.value, "elpd_fold": ef, "mcse_fold": sf}
+
+    def compare_models(self, a: int, b: int) -> dict:
+        """Model a against model b of this run (pcv_compare_models)."""
+        out = pcv_comparison()
+        df = np.zeros(self.K)
+        out.delta_fold = _dptr(df)
+        self._check(self._lib.pcv_compare_models(self._ctx, a, b, ctypes.byref(out)), "pcv_compare_models")
+        return {"delta": out.delta, "sigma2": out.sigma2, "prob_a_better": out.prob_a_better,
+                "mcse": out.mcse, "delta_fold": df}
+
     def shuffle_benchmark(self, R: int, seed: int, per_fold: bool = False):
         mx = np.zeros(R)
-        rep = np.zeros(self.K * R) if per_fold else None
+        rep = np.zeros(self.M * self.K * R) if per_fold else None
         self._check(self._lib.pcv_shuffle_benchmark(self._ctx, R, seed, _dptr(mx), _dptr(rep)),
                     "pcv_shuffle_benchmark")
-        return (mx, rep.reshape(self.K, R)) if per_fold else mx
+        return (mx, rep.reshape(self.M * self.K, R)) if per_fold else mx
 
     def logdensity_grad(self, theta, want_grad: bool = True):
         """theta: [C, d] float64 cuda tensor -> (logp [C], grad [C, d] or None)."""
@@ -388,7 +418,7 @@ class PCV:
     def posthoc(self) -> dict:
         """Two-pass estimates and R-hats (paper's, split, rank-normalised) from the stored draws."""
         out = pcv_posthoc_diag()
-        f = {k: np.zeros(self.K) for k in ("rhat_fold", "split_rhat_fold", "rank_rhat_fold")}
+        f = {k: np.zeros(self.M * self.K) for k in ("rhat_fold", "split_rhat_fold", "rank_rhat_fold")}
         for k, a in f.items():
             setattr(out, k, _dptr(a))
         self._check(self._lib.pcv_posthoc(self._ctx, ctypes.byref(out)), "pcv_posthoc")

@@ -469,7 +469,19 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   const bool hier = md->family == PCV_FAMILY_HIER_LOGISTIC;
   if (hier && (md->n_groups <= 0 || !md->group_of)) return fail(ctx, PCV_ERR_INVALID_ARG, "hierarchical family needs groups");
   const int64_t d = hier ? p + 2 + md->n_groups : p;
-  const int64_t C = static_cast<int64_t>(md->K) * md->L;
+  // models in one launch (Appendix B): M x K posteriors, model-major
+  const int M = md->n_models > 1 ? md->n_models : 1;
+  if (md->n_models < 0) return fail(ctx, PCV_ERR_INVALID_ARG, "n_models must be >= 0");
+  if (M > 1) {
+    if (!md->model_mask) return fail(ctx, PCV_ERR_INVALID_ARG, "n_models > 1 needs model_mask");
+    for (int64_t i = 0; i < static_cast<int64_t>(M) * p; ++i)
+      if (md->model_mask[i] > 1) return fail(ctx, PCV_ERR_INVALID_ARG, "model_mask entries must be 0 or 1");
+    if (hier) return fail(ctx, PCV_ERR_UNSUPPORTED, "several models in one launch: GLM families only");
+    if (md->scores) return fail(ctx, PCV_ERR_UNSUPPORTED, "several models in one launch: no scores");
+    if (md->precision == PCV_PREC_FP64_UNFUSED)
+      return fail(ctx, PCV_ERR_UNSUPPORTED, "several models in one launch: not on the plain fp64 path");
+  }
+  const int64_t C = static_cast<int64_t>(M) * md->K * md->L;
   if (md->chain_offset + C > 0xFFFFFFFFLL) return fail(ctx, PCV_ERR_INVALID_ARG, "global chain ids must fit 32 bits");
   if (!md->inv_mass || !md->init_pos) return fail(ctx, PCV_ERR_INVALID_ARG, "inv_mass and init_pos are required");
   if (md->family == PCV_FAMILY_GAUSSIAN && !(md->sigma > 0 && std::isfinite(md->sigma)))
@@ -563,6 +575,11 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     if (fm->kind == PCV_FOLDS_INTERVALS) h = fp_mix(h, fm->intervals, sizeof(int64_t) * 4 * static_cast<size_t>(K));
     if (fm->kind == PCV_FOLDS_DENSE) h = fp_mix(h, fm->roles, static_cast<size_t>(K) * static_cast<size_t>(n));
     if (hier) h = fp_mix(h, md->group_of, sizeof(int32_t) * static_cast<size_t>(n));
+    if (M > 1) {
+      const int64_t mm = M;
+      h = fp_mix(h, &mm, sizeof mm);
+      h = fp_mix(h, md->model_mask, static_cast<size_t>(M) * static_cast<size_t>(p));
+    }
     ctx->fingerprint = h;
     uint64_t f = 0xcbf29ce484222325ULL;
     const int64_t shape[3] = {fm->kind, n, K};
@@ -579,7 +596,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     if (!ctx->pb) return fail(ctx, PCV_ERR_UNSUPPORTED, "fused VALU path supports p <= 32 (fp64) or p <= 64 (fp32)");
     // few chains and many rows: split rows across workgroups (partial sums
     // reduced per leapfrog step) instead of one fused workgroup per 64 chains
-    const int64_t chain_blocks = (static_cast<int64_t>(md->K) * md->L + 63) / 64;
+    const int64_t chain_blocks = (C + 63) / 64;
     if (chain_blocks < 128 && n >= 2048) ctx->path = PATH_VALU_SPLIT;
   } else if (md->precision == PCV_PREC_BF16X3 || md->precision == PCV_PREC_BF16X5) {
     ctx->path = PATH_MFMA;
@@ -602,6 +619,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   m.d = d;
   m.C = C;
   m.K = K;
+  m.M = M;
+  m.KP = M * K;
   m.L = md->L;
   m.n_groups = hier ? md->n_groups : 0;
   m.sigma = md->family == PCV_FAMILY_GAUSSIAN ? md->sigma : 1.0;
@@ -639,6 +658,11 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   TRY(upload(ctx, &pprec, prior_prec.data(), d));
   TRY(dalloc(ctx, &rowc, n));
   TRY(dalloc(ctx, &fconst, K));
+  if (M > 1) {
+    uint8_t* mk;
+    TRY(upload(ctx, &mk, md->model_mask, static_cast<size_t>(M) * static_cast<size_t>(p)));
+    m.mmask = mk;
+  }
   std::vector<float> y32(y, y + n);
   float* y32d;
   TRY(upload(ctx, &y32d, y32.data(), n));
@@ -722,10 +746,10 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   TRY(dalloc(ctx, &m.nacc, C));
   TRY(dalloc(ctx, &m.ndiv, C));
   TRY(dalloc(ctx, &m.wsum, C));
-  TRY(dalloc(ctx, &m.center, static_cast<size_t>(K)));
+  TRY(dalloc(ctx, &m.center, static_cast<size_t>(m.KP)));
   TRY(dalloc(ctx, &m.t_dev, 1));
   TRY(dalloc(ctx, &m.acc_stat, C));
-  TRY(dalloc(ctx, &ctx->fold_buf, 6 * static_cast<size_t>(K)));
+  TRY(dalloc(ctx, &ctx->fold_buf, 6 * static_cast<size_t>(m.KP)));
   TRY(dalloc(ctx, &ctx->dscal, 8));
   TRY(dalloc(ctx, &ctx->Vpart, C));
 
@@ -860,7 +884,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   CK(launch_fill(m.bmean, 0.0, static_cast<int64_t>(m.D) * C, ctx->st));
   CK(launch_fill(m.bm2, 0.0, static_cast<int64_t>(m.D) * C, ctx->st));
   CK(launch_fill(m.wsum, 0.0, C, ctx->st));
-  CK(launch_fill(m.center, 0.0, K, ctx->st));
+  CK(launch_fill(m.center, 0.0, m.KP, ctx->st));
   if (m.hs1) CK(launch_fill(m.hs1, 0.0, C, ctx->st));
   if (m.hs2) CK(launch_fill(m.hs2, 0.0, static_cast<int64_t>(m.L) * ctx->test_ptr_host[K], ctx->st));
   if (m.dx) CK(launch_fill(m.dx, 0.0, static_cast<int64_t>(m.L) * ctx->test_ptr_host[K], ctx->st));
@@ -979,7 +1003,7 @@ static pcv_status step_run(pcv_ctx ctx, int64_t n_iter) {
 
 static pcv_status run_diag(pcv_ctx ctx, int64_t N, std::vector<double>& fold, double scal[5]) {
   CK(launch_diag(ctx->m, N, ctx->fold_buf, ctx->dscal, ctx->st));
-  fold.resize(6 * static_cast<size_t>(ctx->m.K));
+  fold.resize(6 * static_cast<size_t>(ctx->m.KP));
   CK(hipMemcpyAsync(fold.data(), ctx->fold_buf, sizeof(double) * fold.size(), hipMemcpyDeviceToHost, ctx->st));
   CK(hipMemcpyAsync(scal, ctx->dscal, sizeof(double) * 5, hipMemcpyDeviceToHost, ctx->st));
   CK(hipStreamSynchronize(ctx->st));
@@ -996,7 +1020,7 @@ pcv_status pcv_diagnostics(pcv_ctx ctx, pcv_diag* out) {
   std::vector<double> fold;
   double scal[5];
   TRY(run_diag(ctx, N, fold, scal));
-  const int K = ctx->m.K;
+  const int K = ctx->m.KP;   // posteriors: folds x models
   const double LN = static_cast<double>(ctx->m.L) * N;
   out->elpd = scal[0];
   out->rhat_max = scal[1];
@@ -1024,7 +1048,7 @@ pcv_status pcv_elpd(pcv_ctx ctx, double* elpd, double* mcse, double* elpd_fold, 
   std::vector<double> fold;
   double scal[5];
   TRY(run_diag(ctx, N, fold, scal));
-  const int K = ctx->m.K;
+  const int K = ctx->m.KP;   // posteriors: folds x models
   if (elpd) *elpd = scal[0];
   if (mcse) *mcse = std::sqrt(scal[2]);
   if (elpd_fold) std::memcpy(elpd_fold, fold.data(), sizeof(double) * K);
@@ -1039,7 +1063,7 @@ pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* 
   const int64_t N = std::max<int64_t>(0, ctx->t - ctx->m.n_warmup);
   if (N < 2) return fail(ctx, PCV_ERR_STATE, "fewer than 2 post-warm-up draws");
   double *rep, *mx;
-  const size_t nrep = static_cast<size_t>(ctx->m.K) * R;
+  const size_t nrep = static_cast<size_t>(ctx->m.KP) * R;
   if (hipMalloc(&rep, sizeof(double) * nrep) != hipSuccess) return fail(ctx, PCV_ERR_NOMEM, "hipMalloc failed");
   if (hipMalloc(&mx, sizeof(double) * R) != hipSuccess) {
     (void)hipFree(rep);
@@ -1210,7 +1234,7 @@ struct CkptArray {
 std::vector<CkptArray> ckpt_arrays(pcv_ctx ctx) {
   const DevModel& m = ctx->m;
   const size_t C = m.C, dC = static_cast<size_t>(m.d) * m.C, DC = static_cast<size_t>(m.D) * m.C;
-  const size_t K = static_cast<size_t>(m.K);
+  const size_t K = static_cast<size_t>(m.KP);
   std::vector<CkptArray> a = {{m.q0, 8 * dC},  {m.g0, 8 * dC},  {m.logp0, 8 * C}, {m.s0, 8 * C},
                               {m.Z, 8 * C},    {m.U, 8 * C},    {m.U2, 8 * C},    {m.V, 8 * C},
                               {m.V2, 8 * C},   {m.bmean, 8 * DC}, {m.bm2, 8 * DC}, {m.nacc, 8 * C},
@@ -1419,7 +1443,7 @@ pcv_status pcv_posthoc(pcv_ctx ctx, pcv_posthoc_diag* out) {
   if (!out) return fail(ctx, PCV_ERR_INVALID_ARG, "null output");
   if (!ctx->m.draws) return fail(ctx, PCV_ERR_INVALID_ARG, "draws are not stored (pcv_model.store_draws = 0)");
   const int64_t N = stored_draws(ctx), C = ctx->m.C;
-  const int K = ctx->m.K, L = ctx->m.L;
+  const int K = ctx->m.KP, L = ctx->m.L;   // posteriors: folds x models
   if (N < 4) return fail(ctx, PCV_ERR_STATE, "post-hoc diagnostics need at least 4 stored draws");
   std::vector<double> s(static_cast<size_t>(N) * C);
   int64_t got = 0;
@@ -1449,18 +1473,13 @@ pcv_status pcv_posthoc(pcv_ctx ctx, pcv_posthoc_diag* out) {
 
 // ---- model comparison --------------------------------------------------------
 
-pcv_status pcv_compare(pcv_ctx a, pcv_ctx b, pcv_comparison* out) {
-  if (!usable(a) || !usable(b)) return PCV_ERR_STATE;
-  if (!out) return fail(a, PCV_ERR_INVALID_ARG, "null output");
-  if (a->m.K != b->m.K || a->fold_fp != b->fold_fp)
-    return fail(a, PCV_ERR_INVALID_ARG, "the two models were not evaluated on the same folds");
-  const int K = a->m.K;
-  std::vector<double> ea(K), ma(K), eb(K), mb(K);
-  double ta = 0.0, sa = 0.0, tb = 0.0, sb = 0.0;
-  pcv_status st = pcv_elpd(a, &ta, &sa, ea.data(), ma.data());
-  if (st != PCV_OK) return st;
-  st = pcv_elpd(b, &tb, &sb, eb.data(), mb.data());
-  if (st != PCV_OK) return fail(a, st, std::string("model B: ") + b->err);
+namespace {
+
+// Sections 2.3 and 4.1 over per-fold estimates of two models on the same K
+// folds: Delta and its fold variance (eqs sel-cv, norm-approx), and the
+// Monte Carlo error from both models' fold variances (eq mc-var).
+void compare_folds(const std::vector<double>& ea, const std::vector<double>& ma, const std::vector<double>& eb,
+                   const std::vector<double>& mb, int K, pcv_comparison* out) {
   double delta = 0.0, var_mc = 0.0;
   for (int k = 0; k < K; ++k) {
     delta += ea[k] - eb[k];
@@ -1481,6 +1500,57 @@ pcv_status pcv_compare(pcv_ctx a, pcv_ctx b, pcv_comparison* out) {
   out->mcse = std::sqrt(var_mc);
   if (out->delta_fold)
     for (int k = 0; k < K; ++k) out->delta_fold[k] = ea[k] - eb[k];
+}
+
+}  // namespace
+
+pcv_status pcv_compare(pcv_ctx a, pcv_ctx b, pcv_comparison* out) {
+  if (!usable(a) || !usable(b)) return PCV_ERR_STATE;
+  if (!out) return fail(a, PCV_ERR_INVALID_ARG, "null output");
+  if (a->m.M > 1 || b->m.M > 1)
+    return fail(a, PCV_ERR_INVALID_ARG, "runs with several models: use pcv_compare_models");
+  if (a->m.K != b->m.K || a->fold_fp != b->fold_fp)
+    return fail(a, PCV_ERR_INVALID_ARG, "the two models were not evaluated on the same folds");
+  const int K = a->m.K;
+  std::vector<double> ea(K), ma(K), eb(K), mb(K);
+  double ta = 0.0, sa = 0.0, tb = 0.0, sb = 0.0;
+  pcv_status st = pcv_elpd(a, &ta, &sa, ea.data(), ma.data());
+  if (st != PCV_OK) return st;
+  st = pcv_elpd(b, &tb, &sb, eb.data(), mb.data());
+  if (st != PCV_OK) return fail(a, st, std::string("model B: ") + b->err);
+  compare_folds(ea, ma, eb, mb, K, out);
+  return PCV_OK;
+}
+
+pcv_status pcv_elpd_model(pcv_ctx ctx, int32_t model, double* elpd, double* mcse, double* elpd_fold,
+                          double* mcse_fold) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (model < 0 || model >= ctx->m.M) return fail(ctx, PCV_ERR_INVALID_ARG, "model index out of range");
+  const int K = ctx->m.K, KP = ctx->m.KP;
+  std::vector<double> ef(KP), mf(KP);
+  TRY(pcv_elpd(ctx, nullptr, nullptr, ef.data(), mf.data()));
+  double e = 0.0, v = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double mk = mf[static_cast<size_t>(model) * K + k];
+    e += ef[static_cast<size_t>(model) * K + k];
+    v += mk * mk;
+    if (elpd_fold) elpd_fold[k] = ef[static_cast<size_t>(model) * K + k];
+    if (mcse_fold) mcse_fold[k] = mk;
+  }
+  if (elpd) *elpd = e;
+  if (mcse) *mcse = std::sqrt(v);
+  return PCV_OK;
+}
+
+pcv_status pcv_compare_models(pcv_ctx ctx, int32_t a, int32_t b, pcv_comparison* out) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!out) return fail(ctx, PCV_ERR_INVALID_ARG, "null output");
+  if (a < 0 || a >= ctx->m.M || b < 0 || b >= ctx->m.M) return fail(ctx, PCV_ERR_INVALID_ARG, "model index out of range");
+  const int K = ctx->m.K;
+  std::vector<double> ea(K), ma(K), eb(K), mb(K);
+  TRY(pcv_elpd_model(ctx, a, nullptr, nullptr, ea.data(), ma.data()));
+  TRY(pcv_elpd_model(ctx, b, nullptr, nullptr, eb.data(), mb.data()));
+  compare_folds(ea, ma, eb, mb, K, out);
   return PCV_OK;
 }
 
@@ -1586,8 +1656,10 @@ pcv_status apply_waves(pcv_ctx ctx, int W) {
   return PCV_OK;
 }
 
-// Mean time of the hot kernel: gradient launches at q1 (a copy of the chain
-// positions; q1 is per-trajectory scratch, so the chains are untouched).
+// Mean time of one gradient evaluation at q1 (a copy of the chain positions;
+// q1 and g1 are per-trajectory scratch, so the chains are untouched): the
+// fused kernel's gradient launch, or on the split paths the partials launch
+// plus the reduction of its partials.
 pcv_status time_hot(pcv_ctx ctx, int reps, double* ms) {
   hipEvent_t a = nullptr, b = nullptr;
   CK(hipEventCreate(&a));
@@ -1598,9 +1670,9 @@ pcv_status time_hot(pcv_ctx ctx, int reps, double* ms) {
       return PCV_OK;
     }
     TRY(split_partials(ctx, false));
-    // row-split VALU: the split count also sets the reduction's work, so the
-    // reduction (mode 0: gradient into the scratch g1) is timed with it
-    if (ctx->path == PATH_VALU_SPLIT) TRY(split_reduce(ctx, 0));
+    // the split count also sets the reduction's work, so the reduction
+    // (mode 0: gradient into the scratch g1) is timed with the partials
+    TRY(split_reduce(ctx, 0));
     return PCV_OK;
   };
   pcv_status s = launch();

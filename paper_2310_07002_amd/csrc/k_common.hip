@@ -25,6 +25,7 @@ __global__ void k_reduce(DevModel m, const PT* __restrict__ Gpart, int n_splits,
   const int64_t j = idx / m.C, c = idx - j * m.C;
   double G = 0.0;
   for (int s = 0; s < n_splits; ++s) G += static_cast<double>(Gpart[(static_cast<int64_t>(s) * m.d + j) * m.C + c]);
+  if (!covariate_used(m, c, j)) G = 0.0;   // a masked coefficient: prior only
   const double g = G + prior_grad(m, m.q1[idx], j);
   if (mode == 0) m.g1[idx] = g;
   else leapfrog_update(m, c, j, g, mode == 2);
@@ -33,7 +34,7 @@ __global__ void k_reduce(DevModel m, const PT* __restrict__ Gpart, int n_splits,
 __device__ __forceinline__ double value_finish(const DevModel& m, const double* Vpart, int n_splits, int64_t c) {
   double v = 0.0;
   for (int s = 0; s < n_splits; ++s) v += Vpart[static_cast<int64_t>(s) * m.C + c];
-  return v + m.fold_const[c / m.L] + prior_quad(m, m.q1, c);
+  return v + m.fold_const[fold_of_chain(m, c)] + prior_quad(m, m.q1, c);
 }
 
 __global__ void k_value_finish(DevModel m, const double* Vpart, int n_splits) {
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(64 * ACCEPT_MAX_Y) void k_accept(DevModel m, const 
     const double p = m.pm[o];
     k1 += 0.5 * m.minv[j] * p * p;
   }
-  const int k = static_cast<int>(cc / m.L);
+  const int k = fold_of_chain(m, cc);
   const int beg = m.test_ptr[k], nt = m.test_ptr[k + 1] - beg;
   lp = log_pred_rows<FAM>(m, m.q1, cc, beg + static_cast<int>(static_cast<int64_t>(nt) * y / Y),
                           beg + static_cast<int>(static_cast<int64_t>(nt) * (y + 1) / Y));
@@ -150,7 +151,7 @@ __global__ void k_unfused_resid(DevModel m, double* __restrict__ eta, int64_t c0
   const int64_t col = blockIdx.x;
   if (col >= cc) return;
   const int64_t c = c0 + col;
-  const int k = static_cast<int>(c / m.L);
+  const int k = fold_of_chain(m, c);
   double v = 0.0;
   double* e = eta + col * m.n;
   for (int64_t i = threadIdx.x; i < m.n; i += blockDim.x) {
@@ -521,12 +522,23 @@ hipError_t launch_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uin
   hipLaunchKernelGGL(k_philox, dim3(nblocks(n)), dim3(TPB), 0, st, k0, k1, c0, c1, c2, c3, n, out);
   return hipGetLastError();
 }
-hipError_t launch_center(const DevModel& m, hipStream_t st) {
+// The accumulator-only kernels below (centres, diagnostics, block shuffles)
+// see every posterior as a fold: with several models in one launch, K
+// becomes models x folds (chains k*L .. k*L + L - 1 of posterior k).
+static DevModel posterior_view(const DevModel& m) {
+  DevModel v = m;
+  v.K = m.KP;
+  return v;
+}
+
+hipError_t launch_center(const DevModel& md, hipStream_t st) {
+  const DevModel m = posterior_view(md);
   hipLaunchKernelGGL(k_center, dim3(nblocks(m.K, 64)), dim3(64), 0, st, m);
   return hipGetLastError();
 }
 
-hipError_t launch_diag(const DevModel& m, int64_t N, double* fold_buf, double* out, hipStream_t st) {
+hipError_t launch_diag(const DevModel& md, int64_t N, double* fold_buf, double* out, hipStream_t st) {
+  const DevModel m = posterior_view(md);
   FoldDiag o;
   o.elpd = fold_buf;
   o.rhat = fold_buf + m.K;
@@ -538,8 +550,9 @@ hipError_t launch_diag(const DevModel& m, int64_t N, double* fold_buf, double* o
   hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(1024), 0, st, m.K, o, out);
   return hipGetLastError();
 }
-hipError_t launch_shuffle(const DevModel& m, int64_t N, int R, uint32_t s0, uint32_t s1, double* rep,
+hipError_t launch_shuffle(const DevModel& md, int64_t N, int R, uint32_t s0, uint32_t s1, double* rep,
                           double* repmax, hipStream_t st) {
+  const DevModel m = posterior_view(md);
   hipLaunchKernelGGL(k_shuffle, dim3(nblocks(static_cast<int64_t>(m.K) * R)), dim3(TPB), 0, st, m, N, R, s0, s1,
                      rep);
   hipLaunchKernelGGL(k_shuffle_max, dim3(nblocks(R)), dim3(TPB), 0, st, m.K, R, rep, repmax);

@@ -130,7 +130,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
     const int64_t c = cbase + cb * 16 + l16;
     cidx[cb] = c;
     const int64_t cc = c < m.C ? c : m.C - 1;
-    kf[cb] = static_cast<int>(cc / m.L);
+    kf[cb] = fold_of_chain(m, cc);
     elo[cb] = 0;
     ehi[cb] = 0;
     if (FK == PCV_FOLDS_INTERVALS) {
@@ -150,7 +150,8 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int j = kb * 32 + 8 * g4 + e;
-        const double t = cv ? m.q1[static_cast<int64_t>(j) * m.C + c] * mf_theta_scale<FAM>() : 0.0;
+        const double t = cv && covariate_used(m, c, j)
+                             ? m.q1[static_cast<int64_t>(j) * m.C + c] * mf_theta_scale<FAM>() : 0.0;
         if (NT == 2) {
           const float t32 = static_cast<float>(t);
           const __bf16 h = to_bf16(t32);

@@ -87,7 +87,8 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
   const int32_t* wr = wave_rows ? wave_rows : m.wave_rows;
   T th[PB];
 #pragma unroll
-  for (int j = 0; j < PB; ++j) th[j] = (j < m.p) ? static_cast<T>(m.q1[j * m.C + cc]) : T(0);
+  for (int j = 0; j < PB; ++j)
+    th[j] = (j < m.p && covariate_used(m, cc, j)) ? static_cast<T>(m.q1[j * m.C + cc]) : T(0);
   T mu = 0;
   if (FAM == FAM_HIER) {
     // tau z_g only for the groups of this workgroup's rows; rg cleared for all
@@ -221,7 +222,8 @@ __device__ __forceinline__ void finish_chain(const DevModel& m, int64_t c, int l
   const T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
 #pragma nounroll
   for (int64_t j = 0; j < m.p; ++j)
-    emit(j, static_cast<double>(gfin[j * 64 + lane]) + prior_grad(m, m.q1[j * m.C + c], j));
+    emit(j, (covariate_used(m, c, j) ? static_cast<double>(gfin[j * 64 + lane]) : 0.0) +
+                prior_grad(m, m.q1[j * m.C + c], j));
   if (FAM == FAM_HIER) {
     const double u = m.q1[(m.p + 1) * m.C + c];
     const double tau = exp(u);
@@ -250,7 +252,7 @@ __device__ __forceinline__ void finish_chain(const DevModel& m, int64_t c, int l
   const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;              \
   const bool valid = c < m.C;                                                  \
   const int64_t cc = valid ? c : m.C - 1;                                      \
-  const int k = static_cast<int>(cc / m.L);                                    \
+  const int k = fold_of_chain(m, cc);                                          \
   int elo = 0, ehi = 0;                                                        \
   if (m.fold_kind == PCV_FOLDS_INTERVALS) {                                    \
     elo = m.ivals[4 * k + 2];                                                  \

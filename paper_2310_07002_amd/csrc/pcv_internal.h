@@ -35,6 +35,10 @@ struct DevModel {
   int family, fold_kind;
   int64_t n, p, d, C;
   int K, L, n_groups;
+  // models in one launch (Appendix B): M models x K folds = KP posteriors,
+  // model-major; mmask [M][p] (1 = covariate used), null for one model
+  int M, KP;
+  const uint8_t* mmask;
   double sigma, inv_sigma2, eps;
   int S;
   int64_t n_warmup;
@@ -160,6 +164,15 @@ __device__ __forceinline__ float ell0_32(float y, float eta, float inv_sigma2) {
   return y * eta - (fmaxf(eta, 0.0f) + log1pf(__expf(-fabsf(eta))));
 }
 
+// Data fold of chain c (its posterior index modulo the folds) and whether
+// its model uses covariate j (j < p).
+__host__ __device__ __forceinline__ int fold_of_chain(const DevModel& m, int64_t c) {
+  return static_cast<int>((c / m.L) % m.K);
+}
+__device__ __forceinline__ bool covariate_used(const DevModel& m, int64_t c, int64_t j) {
+  return !m.mmask || m.mmask[(c / m.L / m.K) * m.p + j] != 0;
+}
+
 // Role of row i in fold k: 0 excluded, 1 train, 2 test.
 __device__ __forceinline__ int row_role(const DevModel& m, int64_t i, int k) {
   if (m.fold_kind == PCV_FOLDS_INDEX) {
@@ -184,7 +197,7 @@ __device__ __forceinline__ int row_role(const DevModel& m, int64_t i, int k) {
 __device__ __forceinline__ double eta_row64(const DevModel& m, const double* q, int64_t c, int64_t i) {
   const double* x = m.X64 + i * m.p;
   double e = 0.0;
-  for (int64_t j = 0; j < m.p; ++j) e += x[j] * q[j * m.C + c];
+  for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(m, c, j) ? q[j * m.C + c] : 0.0);
   if (m.family == FAM_HIER) {
     const double mu = q[m.p * m.C + c];
     const double tau = exp(q[(m.p + 1) * m.C + c]);
@@ -215,7 +228,7 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
       e[u] = 0.0;
     }
     for (int64_t j = 0; j < m.p; ++j) {
-      const double qj = q[j * m.C + c];
+      const double qj = covariate_used(m, c, j) ? q[j * m.C + c] : 0.0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) e[u] += m.X64[i[u] * m.p + j] * qj;
     }
@@ -229,7 +242,7 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
     const int64_t i = m.test_rows[t];
     const double* x = m.X64 + i * m.p;
     double e = 0.0;
-    for (int64_t j = 0; j < m.p; ++j) e += x[j] * q[j * m.C + c];
+    for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(m, c, j) ? q[j * m.C + c] : 0.0);
     if (FAM == FAM_HIER) e += mu + tau * q[(m.p + 2 + m.group_of[i]) * m.C + c];
     s += ell0_64<FAM>(m.y64[i], e, m.inv_sigma2) + m.rowc[i];
   }
@@ -239,7 +252,7 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
 // Joint log density of the fold's test rows at q (fp64, with constants).
 template <int FAM>
 __device__ double log_pred_fold(const DevModel& m, const double* q, int64_t c) {
-  const int k = static_cast<int>(c / m.L);
+  const int k = fold_of_chain(m, c);
   return log_pred_rows<FAM>(m, q, c, m.test_ptr[k], m.test_ptr[k + 1]);
 }
 
@@ -385,8 +398,8 @@ __device__ double predictive_draw(const DevModel& m, double eta, W4 w) {
 // HS and DSS sums of one post-warm-up draw at the accepted state q0.
 template <int FAM>
 __device__ void accumulate_scores(const DevModel& m, int64_t c, int64_t t) {
-  const int k = static_cast<int>(c / m.L);
-  const int64_t l = c - static_cast<int64_t>(k) * m.L;
+  const int k = fold_of_chain(m, c);
+  const int64_t l = c % m.L;
   const int beg = m.test_ptr[k], v = m.test_ptr[k + 1] - beg;
   const int64_t o1 = static_cast<int64_t>(m.L) * beg + l * v;
   const uint32_t gc = static_cast<uint32_t>(m.chain_offset + c);

@@ -90,6 +90,8 @@ class Workload:
     rhat_mode: int = 0                         # 0 Welford blocks, 1 shifted sums (Algorithm A2)
     scores: int = 0                            # extra scores accumulated: 1 HS, 2 DSS (bit mask)
     store_draws: int = 0                       # post-warm-up draws of s kept on the device (Algorithm 1)
+    n_models: int = 1                          # nested models in one launch (Appendix B)
+    model_mask: Optional[np.ndarray] = None    # [n_models, p] uint8: covariate j used by model m
     truth: Optional[np.ndarray] = None         # [d]
     x_hi: Optional[np.ndarray] = None          # [n, p] uint16 bf16 bits
     x_lo: Optional[np.ndarray] = None          # [n, p] uint16 bf16 bits
@@ -110,7 +112,7 @@ class Workload:
 
     @property
     def C(self) -> int:
-        return self.K * self.L
+        return self.n_models * self.K * self.L
 
     @property
     def batches_per_block(self) -> int:
@@ -385,6 +387,34 @@ def full_data(w: Workload, L: int = 8, n_warmup: int = 1000) -> Workload:
     sub.n_warmup = n_warmup
     sub.scores = 0
     sub.store_draws = 0
+    return sub
+
+
+def with_models(w: Workload, masks) -> Workload:
+    """Several nested GLMs of w in one launch (Appendix B, parallel model
+    evaluation): masks [M, p] of 0/1, model m uses covariate j iff
+    masks[m, j].  Chains are model-major (M x K x L); every model's chains
+    start where w's do and use its random streams shifted by K*L per model
+    (global chain ids)."""
+    masks = np.ascontiguousarray(np.atleast_2d(masks), dtype=np.uint8)
+    assert masks.shape[1] == w.p and w.family != HIER_LOGISTIC and w.n_models == 1
+    sub = dataclasses.replace(w)
+    sub.name = w.name + f"_{masks.shape[0]}models"
+    sub.n_models = masks.shape[0]
+    sub.model_mask = masks
+    sub.init_pos = np.concatenate([w.init_pos] * masks.shape[0], axis=0)
+    return sub
+
+
+def model_of(w: Workload, m: int) -> Workload:
+    """Model m of a multi-model workload as a workload of its own: the masked
+    covariates' columns zeroed (the masked form of Appendix B) and its global
+    chain ids, so the oracle can replay its chains."""
+    cols = np.flatnonzero(w.model_mask[m] == 0)
+    base = dataclasses.replace(w, n_models=1, model_mask=None)
+    sub = drop_covariates(base, cols, zero=True) if cols.size else dataclasses.replace(base)
+    sub.chain_offset = w.chain_offset + m * w.K * w.L
+    sub.init_pos = w.init_pos[m * w.K * w.L:(m + 1) * w.K * w.L].copy()
     return sub
 
 
