@@ -25,7 +25,7 @@ __global__ void k_reduce(DevModel m, const PT* __restrict__ Gpart, int n_splits,
   const int64_t j = idx / m.C, c = idx - j * m.C;
   double G = 0.0;
   for (int s = 0; s < n_splits; ++s) G += static_cast<double>(Gpart[(static_cast<int64_t>(s) * m.d + j) * m.C + c]);
-  if (!covariate_used(m, c, j)) G = 0.0;   // a masked coefficient: prior only
+  if (!covariate_used(mask_row(m, c), j)) G = 0.0;   // a masked coefficient: prior only
   const double g = G + prior_grad(m, m.q1[idx], j);
   if (mode == 0) m.g1[idx] = g;
   else leapfrog_update(m, c, j, g, mode == 2);

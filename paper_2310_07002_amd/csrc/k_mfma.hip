@@ -73,17 +73,28 @@ __device__ __forceinline__ float mf_resid(float y, float e2, float is2) {
   if (FAM == FAM_POIS) return y - __builtin_amdgcn_exp2f(e2);
   return y - __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-e2));
 }
+
+// Value launches need the residual and the log-likelihood of the same
+// element; one exponential serves both (logistic: t = e^{-|eta|} gives
+// sigma(eta) = (eta >= 0 ? 1 : t) / (1 + t) and log1p(t) from the same
+// 1 + t; Poisson: the mean; Gaussian: the difference y - eta).
 template <int FAM>
-__device__ __forceinline__ float mf_ell0(float y, float e2, float is2) {
+__device__ __forceinline__ void mf_resid_ell0(float y, float e2, float is2, float& r, float& l0) {
   if (FAM == FAM_GAUSS) {
     const float d = y - e2;
-    return -0.5f * d * d * is2;
+    r = d * is2;
+    l0 = -0.5f * d * r;
+  } else if (FAM == FAM_POIS) {
+    const float lam = __builtin_amdgcn_exp2f(e2);
+    r = y - lam;
+    l0 = y * (e2 * LN2_F) - lam;
+  } else {
+    const float t = __builtin_amdgcn_exp2f(-fabsf(e2));    // e^{-|eta|} in (0, 1]
+    const float q = 1.0f + t;
+    r = y - (e2 >= 0.0f ? 1.0f : t) * __builtin_amdgcn_rcpf(q);
+    const float l1p = t > 1e-4f ? __builtin_amdgcn_logf(q) * LN2_F : t * (1.0f - 0.5f * t);
+    l0 = (y * e2 - fmaxf(e2, 0.0f)) * LN2_F - l1p;
   }
-  const float e = e2 * LN2_F;
-  if (FAM == FAM_POIS) return y * e - __builtin_amdgcn_exp2f(e2);
-  const float t = __builtin_amdgcn_exp2f(-fabsf(e2));    // e^{-|eta|} in (0, 1]
-  const float l1p = t > 1e-4f ? __logf(1.0f + t) : t * (1.0f - 0.5f * t);
-  return y * e - (fmaxf(e, 0.0f) + l1p);
 }
 
 template <int FAM, int P, int FWD, bool VALUE, int FK>
@@ -145,12 +156,16 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   for (int cb = 0; cb < 2; ++cb) {
     const int64_t c = cidx[cb];
     const bool cv = c < m.C;
+    const uint8_t* mrow = cv ? mask_row(m, c) : nullptr;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
+      // mask bytes of this lane's 8 covariates in one load (p is a multiple
+      // of 32 here, so the slice is 8-byte aligned); all used without masks
+      const uint64_t mbits = mrow ? *reinterpret_cast<const uint64_t*>(mrow + kb * 32 + 8 * g4) : ~0ull;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int j = kb * 32 + 8 * g4 + e;
-        const double t = cv && covariate_used(m, c, j)
+        const double t = cv && ((mbits >> (8 * e)) & 0xffu)
                              ? m.q1[static_cast<int64_t>(j) * m.C + c] * mf_theta_scale<FAM>() : 0.0;
         if (NT == 2) {
           const float t32 = static_cast<float>(t);
@@ -350,12 +365,11 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
         if (FK == PCV_FOLDS_INDEX) train = rv & (fr8[e] != kf[cb]);
         else train = rv & ((row < elo[cb]) | (row >= ehi[cb]));
         const float x = eta_cur[mh][cb][ii];
-        const float rr = mf_resid<FAM>(yr[e], x, is2);
+        float rr, l0 = 0.f;
+        if (VALUE) mf_resid_ell0<FAM>(yr[e], x, is2, rr, l0);
+        else rr = mf_resid<FAM>(yr[e], x, is2);
         const float r = train ? rr : 0.f;
-        if (VALUE) {
-          const float l0 = mf_ell0<FAM>(yr[e], x, is2);
-          vt[cb] += train ? l0 : 0.f;
-        }
+        if (VALUE) vt[cb] += train ? l0 : 0.f;
         const __bf16 h = to_bf16(r);
         rch[cb][e] = h;
         rcl[cb][e] = to_bf16(r - static_cast<float>(h));

@@ -86,9 +86,10 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
 
   const int32_t* wr = wave_rows ? wave_rows : m.wave_rows;
   T th[PB];
+  const uint8_t* mrow = mask_row(m, cc);
 #pragma unroll
   for (int j = 0; j < PB; ++j)
-    th[j] = (j < m.p && covariate_used(m, cc, j)) ? static_cast<T>(m.q1[j * m.C + cc]) : T(0);
+    th[j] = (j < m.p && covariate_used(mrow, j)) ? static_cast<T>(m.q1[j * m.C + cc]) : T(0);
   T mu = 0;
   if (FAM == FAM_HIER) {
     // tau z_g only for the groups of this workgroup's rows; rg cleared for all
@@ -220,9 +221,10 @@ __device__ __forceinline__ void finish_chain(const DevModel& m, int64_t c, int l
   T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);
   T* rg = zt + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
   const T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
+  const uint8_t* mrow = mask_row(m, c);
 #pragma nounroll
   for (int64_t j = 0; j < m.p; ++j)
-    emit(j, (covariate_used(m, c, j) ? static_cast<double>(gfin[j * 64 + lane]) : 0.0) +
+    emit(j, (covariate_used(mrow, j) ? static_cast<double>(gfin[j * 64 + lane]) : 0.0) +
                 prior_grad(m, m.q1[j * m.C + c], j));
   if (FAM == FAM_HIER) {
     const double u = m.q1[(m.p + 1) * m.C + c];

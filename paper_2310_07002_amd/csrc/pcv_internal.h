@@ -164,14 +164,20 @@ __device__ __forceinline__ float ell0_32(float y, float eta, float inv_sigma2) {
   return y * eta - (fmaxf(eta, 0.0f) + log1pf(__expf(-fabsf(eta))));
 }
 
-// Data fold of chain c (its posterior index modulo the folds) and whether
-// its model uses covariate j (j < p).
+// Data fold of chain c (its posterior index modulo the folds), and the row
+// of the covariate mask of its model (null with one model: every covariate
+// used).  Chain indices fit 32 bits (checked at init), so the divisions are
+// 32-bit; call these once per chain, outside loops over rows or covariates.
 __host__ __device__ __forceinline__ int fold_of_chain(const DevModel& m, int64_t c) {
-  return static_cast<int>((c / m.L) % m.K);
+  const uint32_t post = static_cast<uint32_t>(c) / static_cast<uint32_t>(m.L);
+  return static_cast<int>(m.M > 1 ? post % static_cast<uint32_t>(m.K) : post);
 }
-__device__ __forceinline__ bool covariate_used(const DevModel& m, int64_t c, int64_t j) {
-  return !m.mmask || m.mmask[(c / m.L / m.K) * m.p + j] != 0;
+__device__ __forceinline__ const uint8_t* mask_row(const DevModel& m, int64_t c) {
+  if (!m.mmask) return nullptr;
+  const uint32_t model = static_cast<uint32_t>(c) / static_cast<uint32_t>(m.L * m.K);
+  return m.mmask + static_cast<int64_t>(model) * m.p;
 }
+__device__ __forceinline__ bool covariate_used(const uint8_t* row, int64_t j) { return !row || row[j] != 0; }
 
 // Role of row i in fold k: 0 excluded, 1 train, 2 test.
 __device__ __forceinline__ int row_role(const DevModel& m, int64_t i, int k) {
@@ -197,7 +203,8 @@ __device__ __forceinline__ int row_role(const DevModel& m, int64_t i, int k) {
 __device__ __forceinline__ double eta_row64(const DevModel& m, const double* q, int64_t c, int64_t i) {
   const double* x = m.X64 + i * m.p;
   double e = 0.0;
-  for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(m, c, j) ? q[j * m.C + c] : 0.0);
+  const uint8_t* mrow = mask_row(m, c);
+  for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(mrow, j) ? q[j * m.C + c] : 0.0);
   if (m.family == FAM_HIER) {
     const double mu = q[m.p * m.C + c];
     const double tau = exp(q[(m.p + 1) * m.C + c]);
@@ -215,6 +222,7 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
     mu = q[m.p * m.C + c];
     tau = exp(q[(m.p + 1) * m.C + c]);
   }
+  const uint8_t* mrow = mask_row(m, c);
   double s = 0.0;
   int t = a0;
   // four rows at a time (their loads overlap); each row's arithmetic and the
@@ -228,7 +236,7 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
       e[u] = 0.0;
     }
     for (int64_t j = 0; j < m.p; ++j) {
-      const double qj = covariate_used(m, c, j) ? q[j * m.C + c] : 0.0;
+      const double qj = covariate_used(mrow, j) ? q[j * m.C + c] : 0.0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) e[u] += m.X64[i[u] * m.p + j] * qj;
     }
@@ -242,7 +250,7 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
     const int64_t i = m.test_rows[t];
     const double* x = m.X64 + i * m.p;
     double e = 0.0;
-    for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(m, c, j) ? q[j * m.C + c] : 0.0);
+    for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(mrow, j) ? q[j * m.C + c] : 0.0);
     if (FAM == FAM_HIER) e += mu + tau * q[(m.p + 2 + m.group_of[i]) * m.C + c];
     s += ell0_64<FAM>(m.y64[i], e, m.inv_sigma2) + m.rowc[i];
   }
