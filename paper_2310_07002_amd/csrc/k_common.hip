@@ -23,8 +23,19 @@ __global__ void k_reduce(DevModel m, const PT* __restrict__ Gpart, int n_splits,
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx >= m.d * m.C) return;
   const int64_t j = idx / m.C, c = idx - j * m.C;
+  // loads issued eight at a time, added in split order
+  const PT* gp = Gpart + idx;
+  const int64_t dC = m.d * m.C;
   double G = 0.0;
-  for (int s = 0; s < n_splits; ++s) G += static_cast<double>(Gpart[(static_cast<int64_t>(s) * m.d + j) * m.C + c]);
+  int s = 0;
+  for (; s + 8 <= n_splits; s += 8) {
+    PT t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = gp[(s + u) * dC];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) G += static_cast<double>(t[u]);
+  }
+  for (; s < n_splits; ++s) G += static_cast<double>(gp[s * dC]);
   if (!covariate_used(mask_row(m, c), j)) G = 0.0;   // a masked coefficient: prior only
   const double g = G + prior_grad(m, m.q1[idx], j);
   if (mode == 0) m.g1[idx] = g;
