@@ -120,3 +120,25 @@ def test_masked_models_refused_where_unsupported(dev):
     bad = dataclasses.replace(w2, model_mask=np.full_like(w2.model_mask, 2))
     with pytest.raises(binding.PcvError):
         binding.PCV.from_workload(bad, precision=W.PREC_BF16X3)
+
+
+def test_two_model_run_resumes_from_a_checkpoint(dev, tmp_path):
+    """A two-model launch saved after 30 transitions and resumed in a fresh
+    context continues bit for bit; a context with a different mask refuses
+    the checkpoint."""
+    w = dataclasses.replace(W.fold_subset(W.make("c1"), 0, 30), n_warmup=10, batch_size=10)
+    w2 = W.with_models(w, _masks(w.p, [0, 2]))
+    a = binding.PCV.from_workload(w2)
+    a.step(30)
+    path = str(tmp_path / "two_models.ckpt")
+    a.save(path)
+    a.step(25)
+    b = binding.PCV.from_workload(w2)
+    b.load(path)
+    b.step(25)
+    for x, y in zip(a.get_state(), b.get_state()):
+        np.testing.assert_array_equal(x, y)
+    assert a.elpd_model(1)["elpd"] == b.elpd_model(1)["elpd"]
+    other = binding.PCV.from_workload(W.with_models(w, _masks(w.p, [1])))
+    with pytest.raises(binding.PcvError):
+        other.load(path)
