@@ -83,3 +83,29 @@ def test_family_support_is_checked():
 def test_unsupported_shapes_are_reported():
     w = W.fold_subset(W.make("c1"), 0, 3)
     assert _expect_invalid(w, precision=W.PREC_BF16X3) == 5
+
+
+def test_model_masks_are_validated():
+    """Several models in one launch: masks must be 0/1 and present; the
+    hierarchical family and the scores are refused (host checks, no device)."""
+    w = W.fold_subset(W.make("c1"), 0, 3)
+    m = np.ones((2, w.p), dtype=np.uint8)
+    w2 = W.with_models(w, m)
+    assert _expect_invalid(w2, model_mask=np.full_like(m, 3)) == 1
+    assert _expect_invalid(w2, model_mask=None) == 1
+    assert _expect_invalid(w2, scores=2) == 5                  # PCV_ERR_UNSUPPORTED
+    h = W.fold_subset(W.make("c2"), 0, 2)
+    h2 = dataclasses.replace(h, n_models=2, model_mask=np.ones((2, h.p), dtype=np.uint8),
+                             init_pos=np.concatenate([h.init_pos] * 2))
+    assert _expect_invalid(h2) == 5
+
+
+def test_init_positions_rejects_bad_arguments():
+    lib = binding.load_library()
+    d = np.zeros((3, 2))
+    out = np.zeros((4, 2))
+    ptr = lambda a: a.ctypes.data_as(__import__("ctypes").POINTER(__import__("ctypes").c_double))
+    assert lib.pcv_init_positions(ptr(d), 0, 2, 4, 1, 0, ptr(out)) == 1
+    assert lib.pcv_init_positions(None, 3, 2, 4, 1, 0, ptr(out)) == 1
+    assert lib.pcv_init_positions(ptr(d), 3, 2, 4, 1, 2 ** 32 - 2, ptr(out)) == 1
+    assert lib.pcv_init_positions(ptr(d), 3, 2, 4, 1, 0, ptr(out)) == 0
