@@ -113,3 +113,21 @@ def test_workflow_full_data_tuning_then_cv(dev):
     _say(f"[workflow] eps {r['step_size']:.4f}; elpd {e['elpd']:.4f} +- {e['mcse']:.4f}, exact {exact:.4f}")
     assert abs(e["elpd"] - exact) < 4 * e["mcse"]
     c.close()
+
+
+def test_adapt_on_the_matrix_core_path(dev):
+    """Full-data adaptation of the Poisson GLM (p=64) on the bf16x3 path:
+    the schedule runs through the eager transitions of that path and leaves
+    a finite, positive tuning; the context then steps with it (captured
+    transition graphs)."""
+    w = W.make("c4")
+    f = W.full_data(w, L=8, n_warmup=200)
+    s = binding.PCV.from_workload(f, precision=W.PREC_BF16X3)
+    r = s.adapt(120, 0.8)
+    _say(f"[adapt] c4 bf16x3: eps {r['step_size']:.4f}, Minv range {r['inv_mass'].min():.3g}..{r['inv_mass'].max():.3g}")
+    assert np.isfinite(r["step_size"]) and r["step_size"] > 0
+    assert np.isfinite(r["inv_mass"]).all() and (r["inv_mass"] > 0).all()
+    s.step(10)
+    th, lp, _ = s.get_state()
+    assert np.isfinite(th).all() and np.isfinite(lp).all()
+    s.close()

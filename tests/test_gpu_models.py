@@ -142,3 +142,31 @@ def test_two_model_run_resumes_from_a_checkpoint(dev, tmp_path):
     other = binding.PCV.from_workload(W.with_models(w, _masks(w.p, [1])))
     with pytest.raises(binding.PcvError):
         other.load(path)
+
+
+def test_two_models_on_matrix_cores_track_separate_runs(dev):
+    """Two nested Poisson GLMs (p=64) in one bf16x3 launch stepping through
+    captured transition graphs, against each model run alone (its columns
+    zeroed, its global chain ids): the row-split count may differ between
+    the runs, so positions agree to the bf16x3 tolerance wherever the
+    accept decisions agree, which is nearly everywhere."""
+    w = dataclasses.replace(W.fold_subset(W.make("c4"), 0, 16), n_warmup=3)
+    w2 = W.with_models(w, _masks(w.p, list(range(0, 64, 5))))
+    s = binding.PCV.from_workload(w2, precision=W.PREC_BF16X3)
+    s.step(6)
+    th, _, _ = s.get_state()
+    acc = s.get_accumulators(w.n_blocks)["n_accept"]
+    KL = w.K * w.L
+    for mi in range(2):
+        one = binding.PCV.from_workload(W.model_of(w2, mi), precision=W.PREC_BF16X3)
+        one.step(6)
+        t1, _, _ = one.get_state()
+        a1 = one.get_accumulators(w.n_blocks)["n_accept"]
+        sl = slice(mi * KL, (mi + 1) * KL)
+        same = acc[sl] == a1
+        err = _normwise(th[sl], t1)
+        _say(f"[models] c4 model {mi}: same decisions {same.mean():.3f}, max err (same) {err[same].max():.2e}")
+        assert same.mean() > 0.95
+        assert err[same].max() < 1e-4
+        one.close()
+    s.close()
