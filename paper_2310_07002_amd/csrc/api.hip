@@ -1176,6 +1176,8 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
 
 // ---- checkpoints ---------------------------------------------------------
 
+}  // extern "C"
+
 namespace {
 
 struct CkptHeader {
@@ -1249,6 +1251,8 @@ std::vector<CkptArray> ckpt_arrays(pcv_ctx ctx) {
 }
 
 }  // namespace
+
+extern "C" {
 
 pcv_status pcv_save(pcv_ctx ctx, const char* path) {
   if (!usable(ctx)) return PCV_ERR_STATE;
@@ -1324,6 +1328,8 @@ pcv_status pcv_load(pcv_ctx ctx, const char* path) {
 
 // ---- Hyvaerinen and Dawid-Sebastiani scores ---------------------------------
 
+}  // extern "C"
+
 namespace {
 
 // log|S| and m' S^-1 m by Cholesky (S symmetric, n x n, overwritten); false if
@@ -1355,6 +1361,8 @@ bool chol_logdet_quad(std::vector<double>& S, int n, std::vector<double> m, doub
 }
 
 }  // namespace
+
+extern "C" {
 
 pcv_status pcv_scores(pcv_ctx ctx, double* hs, double* hs_fold, double* dss, double* dss_fold) {
   if (!usable(ctx)) return PCV_ERR_STATE;
@@ -1473,6 +1481,8 @@ pcv_status pcv_posthoc(pcv_ctx ctx, pcv_posthoc_diag* out) {
 
 // ---- model comparison --------------------------------------------------------
 
+}  // extern "C"
+
 namespace {
 
 // Sections 2.3 and 4.1 over per-fold estimates of two models on the same K
@@ -1503,6 +1513,8 @@ void compare_folds(const std::vector<double>& ea, const std::vector<double>& ma,
 }
 
 }  // namespace
+
+extern "C" {
 
 pcv_status pcv_compare(pcv_ctx a, pcv_ctx b, pcv_comparison* out) {
   if (!usable(a) || !usable(b)) return PCV_ERR_STATE;
@@ -1555,6 +1567,8 @@ pcv_status pcv_compare_models(pcv_ctx ctx, int32_t a, int32_t b, pcv_comparison*
 }
 
 // ---- autotuning ------------------------------------------------------------
+
+}  // extern "C"
 
 namespace {
 
@@ -1690,6 +1704,8 @@ pcv_status time_hot(pcv_ctx ctx, int reps, double* ms) {
 }
 
 }  // namespace
+
+extern "C" {
 
 pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, double* ms) {
   if (!usable(ctx)) return PCV_ERR_STATE;

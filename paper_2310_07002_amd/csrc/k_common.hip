@@ -175,7 +175,7 @@ __global__ void k_unfused_resid(DevModel m, double* __restrict__ eta, int64_t c0
   red[threadIdx.x] = v;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if (static_cast<int>(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0 && want_value) Vpart[c] = red[0];
@@ -202,7 +202,7 @@ __global__ void k_foldconst(DevModel m, double prior_const, double* fold_const) 
   red[threadIdx.x] = v;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    if (static_cast<int>(threadIdx.x) < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
   if (threadIdx.x == 0) fold_const[k] = red[0] + prior_const;
@@ -380,7 +380,7 @@ __global__ void k_diag_reduce(int K, FoldDiag o, double* out) {
   r[4][threadIdx.x] = a4;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if (static_cast<int>(threadIdx.x) < s) {
       r[0][threadIdx.x] += r[0][threadIdx.x + s];
       r[1][threadIdx.x] = fmax(r[1][threadIdx.x], r[1][threadIdx.x + s]);
       r[2][threadIdx.x] += r[2][threadIdx.x + s];
