@@ -16,6 +16,8 @@ Also reported on the same JSON line:
                 stream during the timed region, against the dense bf16 peak;
                 HBM traffic from committed rocprofv3 counter summaries if any
   cpu_baseline  the fp64 CPU oracle on a bounded sample of the same workload
+  parity_vs_oracle  the device's log density and gradient against the oracle
+                at the starting positions of that sample's chains
   plain_fp64    the unfused fp64 library path (DGEMM + materialised eta) on
                 the same workload, a few steps, and the speedup over it
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5]
@@ -52,6 +54,29 @@ def workload_label(w, prec):
             f"eps={w.step_size} precision={prec}")
 
 
+def baseline_folds(w) -> int:
+    """Folds of the bounded CPU sample (the first ones of the workload)."""
+    return max(1, min(w.K, 16 if w.n * w.p <= 1e6 else 4))
+
+
+def oracle_parity(w, theta, lp_dev, g_dev):
+    """Error of the device's log density and gradient against the fp64 oracle
+    at the same positions, on the chains of the CPU sample."""
+    from oracle import folds, model
+    from paper_2310_07002_amd import workloads as W
+    sub = W.fold_subset(w, 0, baseline_folds(w))
+    roles = folds.roles_of(sub)
+    foc = np.arange(sub.C) // sub.L
+    th = theta[:sub.C]
+    lp_o = model.log_density(sub, th, roles, foc)
+    g_o = model.grad_log_density(sub, th, roles, foc)
+    rel_v = np.abs(lp_dev[:sub.C] - lp_o) / np.abs(lp_o)
+    rel_g = np.linalg.norm(g_dev[:sub.C] - g_o, axis=1) / np.linalg.norm(g_o, axis=1)
+    return {"reference": "fp64 oracle", "chains": sub.C, "at": "the chains' starting positions",
+            "logp_rel_max": float(rel_v.max()), "grad_normwise_rel_max": float(rel_g.max()),
+            "grad_normwise_rel_median": float(np.median(rel_g))}
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The oracle as it stands, on a bounded sample: the first folds of the
     same workload (same chains, same random streams), as many transitions as
@@ -64,7 +89,7 @@ def cpu_baseline(w, budget_s=15.0):
         threads = max((i.get("num_threads") or 0) for i in threadpool_info()) or None
     except Exception:
         pass
-    k_sub = max(1, min(w.K, 16 if w.n * w.p <= 1e6 else 4))
+    k_sub = baseline_folds(w)
     sub = W.fold_subset(w, 0, k_sub)
     run = sampler.start(sub)
     t0 = time.perf_counter()
@@ -215,6 +240,15 @@ def main():
         line["autotune"] = tune
 
     d = s.diagnostics() if args.warmup + args.steps > w.n_warmup + 1 else None
+    dev_eval = None
+    if not args.no_cpu_baseline:
+        # log pi and its gradient at the starting positions, checked against
+        # the oracle on the CPU sample's chains in the baseline leg
+        lp_d, g_d = s.logdensity_grad(torch.tensor(w.init_pos, device="cuda"))
+        torch.cuda.synchronize()
+        n_keep = baseline_folds(w) * w.L
+        dev_eval = (lp_d[:n_keep].cpu().numpy(), g_d[:n_keep].cpu().numpy())
+        del lp_d, g_d
     s.close()
     del s
 
@@ -266,6 +300,7 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle, bounded sample)")
         line["cpu_baseline"] = cpu_baseline(w)
+        line["parity_vs_oracle"] = oracle_parity(w, w.init_pos, *dev_eval)
     # the same number of transitions at the other paths' measured rates
     tr = line.get("time_to_rhat_max_1.01")
     if tr and tr.get("draws") is not None and tr.get("reached", True):
