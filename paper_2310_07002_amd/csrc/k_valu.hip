@@ -5,6 +5,8 @@
 // interact (Section 3.3).  The W waves of the workgroup split the rows; each
 // row of X is read once per wave with scalar loads and broadcast to the 64
 // chains.  Used for narrow designs (p <= 32 in fp64, p <= 64 in fp32).
+#include <type_traits>
+
 #include "pcv_internal.h"
 
 namespace pcv {
@@ -114,8 +116,10 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
   int gcur = -1, gfirst = -1;
   T racc = T(0), zcur = T(0);
   // One row: its coefficients xv, response y, group g and fold id f (the
-  // fold id is used by index-coded folds only).
-  auto row = [&](int64_t i, const T (&xv)[PB], T y, int g, int f) {
+  // fold id is used by index-coded folds only); the fold encoding is a
+  // compile-time constant of the row loop that calls it.
+  auto row = [&](auto fold_kind, int64_t i, const T (&xv)[PB], T y, int g, int f) {
+    constexpr int FKR = decltype(fold_kind)::value;
     T eta = T(0);
 #pragma unroll
     for (int j = 0; j < PB; ++j) eta += xv[j] * th[j];
@@ -136,8 +140,8 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
       eta += mu + zcur;
     }
     bool train;
-    if (m.fold_kind == PCV_FOLDS_INDEX) train = f != k;
-    else if (m.fold_kind == PCV_FOLDS_INTERVALS) train = (i < elo) || (i >= ehi);
+    if constexpr (FKR == PCV_FOLDS_INDEX) train = f != k;
+    else if constexpr (FKR == PCV_FOLDS_INTERVALS) train = (i < elo) || (i >= ehi);
     else train = m.roles[static_cast<int64_t>(k) * m.n + i] == 1;
     const T r = train ? vresid<FAM, T>(y, eta, is2) : T(0);
 #pragma unroll
@@ -147,14 +151,21 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
       if (train) val += static_cast<double>(vell0<FAM, T>(y, eta, is2));
     }
   };
-  for (int64_t i = r0; i < r1; ++i) {
-    const T* xr = Xv + i * PB;
-    T xv[PB];
+  // the fold encoding is decided once, outside the row loop
+  auto rows = [&](auto fold_kind) {
+    constexpr int FKR = decltype(fold_kind)::value;
+    for (int64_t i = r0; i < r1; ++i) {
+      const T* xr = Xv + i * PB;
+      T xv[PB];
 #pragma unroll
-    for (int j = 0; j < PB; ++j) xv[j] = xr[j];
-    row(i, xv, ValuY<T>::get(m, i), FAM == FAM_HIER ? m.group_of[i] : 0,
-        m.fold_kind == PCV_FOLDS_INDEX ? m.fold_index[i] : 0);
-  }
+      for (int j = 0; j < PB; ++j) xv[j] = xr[j];
+      row(fold_kind, i, xv, ValuY<T>::get(m, i), FAM == FAM_HIER ? m.group_of[i] : 0,
+          FKR == PCV_FOLDS_INDEX ? m.fold_index[i] : 0);
+    }
+  };
+  if (m.fold_kind == PCV_FOLDS_INDEX) rows(std::integral_constant<int, PCV_FOLDS_INDEX>{});
+  else if (m.fold_kind == PCV_FOLDS_INTERVALS) rows(std::integral_constant<int, PCV_FOLDS_INTERVALS>{});
+  else rows(std::integral_constant<int, PCV_FOLDS_DENSE>{});
   if (FAM == FAM_HIER) {
     int glast = -1;
     if (gcur >= 0) {
