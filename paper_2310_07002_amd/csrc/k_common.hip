@@ -86,11 +86,15 @@ __global__ __launch_bounds__(64 * WIDE_MAX_Y) void k_momentum(DevModel m, int64_
 // the test, logp0 and s0 (the proposal's log predictive when accepted).
 // Phase 3 (all waves): q0, g0 := q1, g1 for accepted chains.  Phase 4
 // (wave 0): accumulation, which reads the selected q0 for the scores.
-constexpr int ACCEPT_MAX_Y = 8;   // the scores' predictive draws need the registers of 512-thread groups
+// Waves per workgroup of k_accept: the Gaussian family's score draws need
+// the registers of 512-thread groups; the others fit 1024-thread groups.
 template <int FAM>
-__global__ __launch_bounds__(64 * ACCEPT_MAX_Y) void k_accept(DevModel m, const double* __restrict__ Vpart,
-                                                              int n_splits, int64_t t) {
-  __shared__ double red[4][ACCEPT_MAX_Y][64];
+constexpr int accept_max_y() { return FAM == FAM_GAUSS ? 8 : WIDE_MAX_Y; }
+
+template <int FAM>
+__global__ __launch_bounds__(64 * accept_max_y<FAM>()) void k_accept(DevModel m, const double* __restrict__ Vpart,
+                                                                     int n_splits, int64_t t) {
+  __shared__ double red[4][accept_max_y<FAM>()][64];
   __shared__ int acc_s[64];
   const int lane = threadIdx.x & 63, y = threadIdx.x >> 6, Y = blockDim.x >> 6;
   const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;
@@ -493,7 +497,7 @@ hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st) {
   return hipGetLastError();
 }
 hipError_t launch_accept(const DevModel& m, const double* V, int ns, int64_t t, hipStream_t st) {
-  const int Y = std::min(wide_waves(m.C), ACCEPT_MAX_Y);
+  const int Y = std::min(wide_waves(m.C), m.family == FAM_GAUSS ? accept_max_y<FAM_GAUSS>() : WIDE_MAX_Y);
   PCV_FAM_DISPATCH(m.family, k_accept, dim3(nblocks(m.C, 64)), dim3(64 * Y), st, m, V, ns, t);
   return hipGetLastError();
 }
