@@ -72,7 +72,10 @@ enum {
                                every other fold; -1 = train in every fold           */
   PCV_FOLDS_INTERVALS = 1,  /* intervals[K][4] = (test_lo, test_hi, excl_lo, excl_hi):
                                [test_lo,test_hi) test, rest of [excl_lo,excl_hi)
-                               excluded, every other row train (hv-block, blocked) */
+                               excluded, every other row train (hv-block, blocked);
+                               when both ranges are non-empty they must overlap
+                               or touch (one non-train range per fold), else
+                               PCV_ERR_INVALID_ARG                                  */
   PCV_FOLDS_DENSE = 2       /* roles[K][n]: 0 excluded, 1 train, 2 test            */
 };
 

@@ -536,13 +536,23 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
       const int64_t* v = fm->intervals + 4 * k;
       if (v[0] < 0 || v[1] < v[0] || v[1] > n || v[2] < 0 || v[3] < v[2] || v[3] > n)
         return fail(ctx, PCV_ERR_INVALID_ARG, "intervals out of range");
-      for (int q = 0; q < 4; ++q) ivals[4 * k + q] = static_cast<int32_t>(v[q]);
+      // The kernels take a fold's non-train rows as one range: store the hull
+      // of the test and excluded ranges, which must touch or overlap when
+      // both are non-empty.
+      int64_t nlo = v[2], nhi = v[3];
+      if (v[1] > v[0]) {
+        if (v[3] > v[2] && (v[1] < v[2] || v[3] < v[0]))
+          return fail(ctx, PCV_ERR_INVALID_ARG, "intervals: test and excluded ranges of a fold must overlap or touch");
+        nlo = v[3] > v[2] ? std::min(v[0], v[2]) : v[0];
+        nhi = v[3] > v[2] ? std::max(v[1], v[3]) : v[1];
+      }
+      ivals[4 * k + 0] = static_cast<int32_t>(v[0]);
+      ivals[4 * k + 1] = static_cast<int32_t>(v[1]);
+      ivals[4 * k + 2] = static_cast<int32_t>(nlo);
+      ivals[4 * k + 3] = static_cast<int32_t>(nhi);
       for (int64_t i = v[0]; i < v[1]; ++i) test_rows.push_back(static_cast<int32_t>(i));
       test_ptr[k + 1] = static_cast<int32_t>(test_rows.size());
-      const int64_t lo = std::min(v[0], v[2]), hi = std::max(v[1], v[3]);
-      const bool overlap = !(v[1] < v[2] || v[3] < v[0]);
-      const int64_t removed = overlap ? hi - lo : (v[1] - v[0]) + (v[3] - v[2]);
-      train_cnt[k] = n - removed;
+      train_cnt[k] = n - (nhi - nlo);
     }
   } else if (fm->kind == PCV_FOLDS_DENSE) {
     if (!fm->roles) return fail(ctx, PCV_ERR_INVALID_ARG, "roles missing");

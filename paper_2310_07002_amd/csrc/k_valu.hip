@@ -61,6 +61,9 @@ __host__ __device__ constexpr int valu_jc() {
   return (sizeof(T) == 8 ? 4 : 8) < PB ? (sizeof(T) == 8 ? 4 : 8) : PB;
 }
 
+// Row-loop fold test for rows on which every lane of the wave trains.
+constexpr int ALL_TRAIN = -1;
+
 // Groups [glo, ghi] spanned by the rows [wr[0], wr[W]) of a workgroup (rows
 // are sorted by group); empty range (glo > ghi) when it has no rows.
 __device__ __forceinline__ void block_groups(const DevModel& m, const int32_t* wr, int W, int& glo, int& ghi) {
@@ -140,7 +143,8 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
       eta += mu + zcur;
     }
     bool train;
-    if constexpr (FKR == PCV_FOLDS_INDEX) train = f != k;
+    if constexpr (FKR == ALL_TRAIN) train = true;
+    else if constexpr (FKR == PCV_FOLDS_INDEX) train = f != k;
     else if constexpr (FKR == PCV_FOLDS_INTERVALS) train = (i < elo) || (i >= ehi);
     else train = m.roles[static_cast<int64_t>(k) * m.n + i] == 1;
     const T r = train ? vresid<FAM, T>(y, eta, is2) : T(0);
@@ -152,9 +156,13 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
     }
   };
   // the fold encoding is decided once, outside the row loop
-  auto rows = [&](auto fold_kind) {
+  auto rows = [&](auto fold_kind, int64_t ra, int64_t rb) {
     constexpr int FKR = decltype(fold_kind)::value;
-    for (int64_t i = r0; i < r1; ++i) {
+    // GLM rows: four rows per trip puts their scalar loads under one wait.
+    // The hierarchical row carries a group-change branch and gains nothing.
+    constexpr int RU = FAM == FAM_HIER ? 1 : 4;
+#pragma unroll RU
+    for (int64_t i = ra; i < rb; ++i) {
       const T* xr = Xv + i * PB;
       T xv[PB];
 #pragma unroll
@@ -163,9 +171,32 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
           FKR == PCV_FOLDS_INDEX ? m.fold_index[i] : 0);
     }
   };
-  if (m.fold_kind == PCV_FOLDS_INDEX) rows(std::integral_constant<int, PCV_FOLDS_INDEX>{});
-  else if (m.fold_kind == PCV_FOLDS_INTERVALS) rows(std::integral_constant<int, PCV_FOLDS_INTERVALS>{});
-  else rows(std::integral_constant<int, PCV_FOLDS_DENSE>{});
+  if (m.fold_kind == PCV_FOLDS_INDEX) {
+    rows(std::integral_constant<int, PCV_FOLDS_INDEX>{}, r0, r1);
+  } else if (m.fold_kind == PCV_FOLDS_INTERVALS && FAM == FAM_HIER) {
+    rows(std::integral_constant<int, PCV_FOLDS_INTERVALS>{}, r0, r1);
+  } else if (m.fold_kind == PCV_FOLDS_INTERVALS) {
+    // Interval folds exclude one contiguous row range per lane.  Outside the
+    // union hull [xlo, xhi) of the wave's ranges every lane trains on every
+    // row, so those rows skip the per-lane test; same rows, same order.
+    // (GLM families only: the extra row loops cost the hierarchical kernel
+    // registers.)
+    int xlo = elo < ehi ? elo : INT32_MAX, xhi = elo < ehi ? ehi : INT32_MIN;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      xlo = min(xlo, __shfl_xor(xlo, o));
+      xhi = max(xhi, __shfl_xor(xhi, o));
+    }
+    xlo = __builtin_amdgcn_readfirstlane(xlo);
+    xhi = __builtin_amdgcn_readfirstlane(xhi);
+    const int64_t ra = xlo < r0 ? r0 : (xlo > r1 ? r1 : static_cast<int64_t>(xlo));
+    const int64_t rb = xhi < ra ? ra : (xhi > r1 ? r1 : static_cast<int64_t>(xhi));
+    rows(std::integral_constant<int, ALL_TRAIN>{}, r0, ra);
+    rows(std::integral_constant<int, PCV_FOLDS_INTERVALS>{}, ra, rb);
+    rows(std::integral_constant<int, ALL_TRAIN>{}, rb, r1);
+  } else {
+    rows(std::integral_constant<int, PCV_FOLDS_DENSE>{}, r0, r1);
+  }
   if (FAM == FAM_HIER) {
     int glast = -1;
     if (gcur >= 0) {

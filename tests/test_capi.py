@@ -109,3 +109,18 @@ def test_init_positions_rejects_bad_arguments():
     assert lib.pcv_init_positions(None, 3, 2, 4, 1, 0, ptr(out)) == 1
     assert lib.pcv_init_positions(ptr(d), 3, 2, 4, 1, 2 ** 32 - 2, ptr(out)) == 1
     assert lib.pcv_init_positions(ptr(d), 3, 2, 4, 1, 0, ptr(out)) == 0
+
+
+def test_interval_folds_need_one_non_train_range():
+    """Interval folds: a test block and an exclusion range that neither
+    overlap nor touch would give a fold two non-train ranges; refused on the
+    host (the touching and empty-exclusion forms are accepted and checked
+    against the oracle on the device)."""
+    w = W.fold_subset(W.make("c3"), 0, 4)
+    iv = w.intervals.copy()
+    k = 2
+    lo, hi = int(iv[k, 0]), int(iv[k, 1])
+    iv[k] = (lo, hi, hi + 3, hi + 6)
+    assert _expect_invalid(w, intervals=iv) == 1
+    iv[k] = (lo, hi, max(0, lo - 9), lo - 4)
+    assert _expect_invalid(w, intervals=iv) == 1

@@ -137,6 +137,57 @@ def test_interval_folds_on_matrix_cores(dev, prec, tol_v, tol_g):
     assert rel_g.max() < tol_g
 
 
+def _mixed_intervals(w, h=6):
+    """Interval folds in four forms, cycling over the folds so that one
+    wave's lanes mix them: no exclusion range, an exclusion range touching
+    the test block from above or from below, and a buffer on both sides."""
+    iv = w.intervals.copy()
+    for k in range(w.K):
+        lo, hi = int(iv[k, 0]), int(iv[k, 1])
+        iv[k] = [(lo, hi, lo, lo), (lo, hi, hi, min(w.n, hi + 3)), (lo, hi, max(0, lo - 4), lo),
+                 (lo, hi, max(0, lo - h), min(w.n, hi + h))][k % 4]
+    return dataclasses.replace(w, intervals=iv)
+
+
+@pytest.mark.parametrize("path", ["split", "fused", "mfma"])
+def test_interval_fold_forms(dev, path):
+    """The four interval forms on the row-split VALU path (all 4996 rows),
+    the fused VALU path (rows cut under 2048) and the matrix cores (blocked
+    folds recoded as intervals): value and gradient against the oracle, and
+    on the VALU paths three whole transitions replayed."""
+    if path == "mfma":
+        w = W.fold_subset(W.make("c5"), 100, 132)
+        iv = np.zeros((w.K, 4), dtype=np.int64)
+        for k in range(w.K):
+            rows = np.flatnonzero(w.fold_index == k)
+            iv[k] = (rows.min(), rows.max() + 1, 0, 0)
+        w = dataclasses.replace(w, fold_kind=W.FOLDS_INTERVALS, intervals=iv, fold_index=None)
+        tol, prec = 1e-5, W.PREC_BF16X5
+    else:
+        w = W.fold_subset(W.make("c3"), 296, 336)
+        if path == "fused":
+            n = 1800
+            w = dataclasses.replace(w, X=w.X[:n], y=w.y[:n],
+                                    intervals=np.minimum(w.intervals, n))
+        tol, prec = 1e-12, W.PREC_FP64
+    w = dataclasses.replace(_mixed_intervals(w), n_warmup=2)
+    _say(f"[interval forms] {path} n={w.n} C={w.C}")
+    theta = _theta_near_init(w, seed=6)
+    lp_o, g_o = _oracle_eval(w, theta)
+    s = binding.PCV.from_workload(w, precision=prec)
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    rel_v = np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)
+    rel_g = _normwise(g.cpu().numpy(), g_o)
+    _say(f"    logp rel max {rel_v.max():.2e}  grad normwise max {rel_g.max():.2e}")
+    assert rel_v.max() < tol
+    assert rel_g.max() < tol
+    if path != "mfma":
+        run, s2 = _replay(w, 3, dev, prec=prec)
+        th, _, sv = s2.get_state()
+        np.testing.assert_allclose(th, run.state.q, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(sv, run.state.s, rtol=1e-10, atol=1e-12)
+
+
 def test_dense_fold_encoding_matches_index(dev):
     w = W.fold_subset(W.make("c1"), 0, 30)
     wd = W.with_dense_roles(w)
