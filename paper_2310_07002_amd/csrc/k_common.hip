@@ -23,17 +23,25 @@ __global__ void k_reduce(DevModel m, const PT* __restrict__ Gpart, int n_splits,
   const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (idx >= m.d * m.C) return;
   const int64_t j = idx / m.C, c = idx - j * m.C;
-  // loads issued eight at a time, added in split order
+  // loads issued sixteen at a time, added in split order
   const PT* gp = Gpart + idx;
   const int64_t dC = m.d * m.C;
   double G = 0.0;
   int s = 0;
-  for (; s + 8 <= n_splits; s += 8) {
+  for (; s + 16 <= n_splits; s += 16) {
+    PT t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = gp[(s + u) * dC];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) G += static_cast<double>(t[u]);
+  }
+  if (s + 8 <= n_splits) {
     PT t[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) t[u] = gp[(s + u) * dC];
 #pragma unroll
     for (int u = 0; u < 8; ++u) G += static_cast<double>(t[u]);
+    s += 8;
   }
   for (; s < n_splits; ++s) G += static_cast<double>(gp[s * dC]);
   if (!covariate_used(mask_row(m, c), j)) G = 0.0;   // a masked coefficient: prior only

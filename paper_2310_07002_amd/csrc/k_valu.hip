@@ -434,12 +434,20 @@ __global__ void k_valu_finish(DevModel m, const double* __restrict__ Gpart, cons
   const double* gp = Gpart + idx;
   double v = 0.0;
   int sp = s0;
-  for (; sp + 8 <= s1 + 1; sp += 8) {   // loads issued eight at a time, added in split order
+  for (; sp + 16 <= s1 + 1; sp += 16) {   // loads issued sixteen at a time, added in split order
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = gp[(sp + u) * dC];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v += t[u];
+  }
+  if (sp + 8 <= s1 + 1) {
     double t[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) t[u] = gp[(sp + u) * dC];
 #pragma unroll
     for (int u = 0; u < 8; ++u) v += t[u];
+    sp += 8;
   }
   for (; sp <= s1; ++sp) v += gp[sp * dC];
   double g;

@@ -224,35 +224,51 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
   }
   const uint8_t* mrow = mask_row(m, c);
   double s = 0.0;
-  int t = a0;
-  // four rows at a time (their loads overlap); each row's arithmetic and the
-  // order of the sum over rows are those of the one-row loop below
-  for (; t + 4 <= a1; t += 4) {
+  // Four rows at a time (a last group of two or three masked, a last single
+  // row on its own), LPB coefficients per batch of loads, so that loads
+  // overlap; each row's arithmetic and the order of the sum over rows are
+  // those of a plain row-by-row loop.
+  constexpr int LPB = 2;
+  for (int t = a0; t < a1; t += 4) {
+    if (t + 1 == a1) {
+      const int64_t i = m.test_rows[t];
+      const double* x = m.X64 + i * m.p;
+      double e = 0.0;
+      for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(mrow, j) ? q[j * m.C + c] : 0.0);
+      if (FAM == FAM_HIER) e += mu + tau * q[(m.p + 2 + m.group_of[i]) * m.C + c];
+      s += ell0_64<FAM>(m.y64[i], e, m.inv_sigma2) + m.rowc[i];
+      break;
+    }
     int64_t i[4];
     double e[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      i[u] = m.test_rows[t + u];
+      i[u] = m.test_rows[t + u < a1 ? t + u : t];
       e[u] = 0.0;
     }
-    for (int64_t j = 0; j < m.p; ++j) {
-      const double qj = covariate_used(mrow, j) ? q[j * m.C + c] : 0.0;
+    for (int64_t j0 = 0; j0 < m.p; j0 += LPB) {
+      double qj[LPB], xv[4][LPB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) e[u] += m.X64[i[u] * m.p + j] * qj;
+      for (int v = 0; v < LPB; ++v) {
+        const int64_t j = j0 + v < m.p ? j0 + v : j0;
+        qj[v] = covariate_used(mrow, j) ? q[j * m.C + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u][v] = m.X64[i[u] * m.p + j];
+      }
+#pragma unroll
+      for (int v = 0; v < LPB; ++v)
+        if (j0 + v < m.p) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) e[u] += xv[u][v] * qj[v];
+        }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (FAM == FAM_HIER) e[u] += mu + tau * q[(m.p + 2 + m.group_of[i[u]]) * m.C + c];
-      s += ell0_64<FAM>(m.y64[i[u]], e[u], m.inv_sigma2) + m.rowc[i[u]];
+      if (t + u < a1) {
+        if (FAM == FAM_HIER) e[u] += mu + tau * q[(m.p + 2 + m.group_of[i[u]]) * m.C + c];
+        s += ell0_64<FAM>(m.y64[i[u]], e[u], m.inv_sigma2) + m.rowc[i[u]];
+      }
     }
-  }
-  for (; t < a1; ++t) {
-    const int64_t i = m.test_rows[t];
-    const double* x = m.X64 + i * m.p;
-    double e = 0.0;
-    for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(mrow, j) ? q[j * m.C + c] : 0.0);
-    if (FAM == FAM_HIER) e += mu + tau * q[(m.p + 2 + m.group_of[i]) * m.C + c];
-    s += ell0_64<FAM>(m.y64[i], e, m.inv_sigma2) + m.rowc[i];
   }
   return s;
 }
