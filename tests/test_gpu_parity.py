@@ -571,12 +571,17 @@ def test_full_size_sampled_parity(dev, name, prec, tol_g):
     assert worst_g < tol_g
 
 
-def test_graph_replay_matches_eager(dev):
+@pytest.mark.parametrize("name,folds_,prec", [("c4", (0, 40), "bf16x3"), ("c3", (0, 40), "fp64"),
+                                             ("c2", (0, 10), "fp32")])
+def test_graph_replay_matches_eager(dev, name, folds_, prec):
     """Transitions replayed from the captured graph equal eager launches of
-    the same kernels, replay after replay, with eager work in between."""
-    w = dataclasses.replace(W.fold_subset(W.make("c4"), 0, 40), n_warmup=3)
-    g = binding.PCV.from_workload(w, precision=W.PREC_BF16X3)        # graph replays
-    e = binding.PCV.from_workload(w, precision=W.PREC_BF16X3)        # eager (timing on)
+    the same kernels, replay after replay, with eager work in between: the
+    matrix-core path (c4) and the row-split VALU path for interval folds
+    (c3) and the hierarchical family (c2)."""
+    w = dataclasses.replace(W.fold_subset(W.make(name), *folds_), n_warmup=3)
+    _say(f"[graph] {name} {prec} C={w.C}")
+    g = binding.PCV.from_workload(w, precision=PREC[prec])           # graph replays
+    e = binding.PCV.from_workload(w, precision=PREC[prec])           # eager (timing on)
     e.timing_enable(True)
     for rep in range(4):
         g.step(2)
