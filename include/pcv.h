@@ -88,7 +88,10 @@ typedef struct pcv_folds {
 
 /* Encoding of X passed to pcv_init. */
 enum {
-  PCV_X_FP64 = 0,        /* n*p fp64, row-major                                      */
+  PCV_X_FP64 = 0,        /* n*p fp64, row-major.  The bf16 precisions round each
+                            entry to fp32 and store it as the bf16 pair hi + lo,
+                            which keeps about 16 significant bits (relative error
+                            <= 2^-16); exact for designs given as two planes      */
   PCV_X_BF16_HILO = 1    /* two bf16 planes (uint16 bit patterns), hi then lo, each
                             n*p row-major; the design is hi + lo, summed exactly in
                             fp64 (a stored split such as the synthetic c4/c5 designs) */
@@ -205,10 +208,18 @@ pcv_status pcv_init(pcv_ctx* out, const pcv_model* model, const void* X, const d
  * default stream).  The stream must outlive its use by ctx. */
 pcv_status pcv_set_stream(pcv_ctx ctx, void* hip_stream);
 
-/* Advance every chain n_iter HMC transitions (n_iter >= 0).  The first
- * model->n_warmup transitions overall are warm-up and are not accumulated.
- * Asynchronous on the context stream.  Divergent transitions are counted,
- * not errors. */
+/* Advance every chain n_iter HMC transitions (n_iter >= 0): the sampling
+ * loop of Algorithm A2 (Appendix A) over all folds at once, each transition
+ * one fixed-trajectory HMC step of every chain in lock-step (Section 3.3):
+ * momentum refresh, n_leapfrog leapfrog steps of masked value-and-gradient
+ * evaluations (Appendix B), Metropolis accept, and for post-warm-up
+ * transitions the log predictive of the fold's test set and the online
+ * accumulators (streaming log-sum-exp, batch means, per-block R-hat
+ * statistics).  The first model->n_warmup transitions overall are warm-up
+ * and are not accumulated.  Asynchronous on the context stream.  Divergent
+ * transitions are counted, not errors.  Errors: PCV_ERR_INVALID_ARG for
+ * n_iter < 0 or a transition count beyond 32 bits; PCV_ERR_STATE for a dead
+ * context; PCV_ERR_DEVICE if a launch fails. */
 pcv_status pcv_step(pcv_ctx ctx, int64_t n_iter);
 
 /* Convergence diagnostics of the LogS estimate (Section 4) from the online
@@ -375,15 +386,18 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
  * transitions to the file `path`:
  * - the accepted positions, gradients, log pi and log predictive of every chain;
  * - every online accumulator (Algorithm A2) and the accept/divergence counters;
+ * - the step size and diagonal inverse mass in force (pcv_adapt changes both);
  * - the transition count.
  * The write goes to `path`.tmp first and is renamed into place.
  * pcv_load restores such a file into a context made by pcv_init with the
  * same model, data, folds and precision (checked against a fingerprint of
- * X, y and the folds).  Because every random number is keyed by (seed,
- * chain, transition), the resumed run continues exactly as the original
- * would have.  Errors: PCV_ERR_INVALID_ARG for an unwritable or unreadable
- * path, a file of another run, or a truncated or corrupted file (the ctx is
- * unchanged then); PCV_ERR_DEVICE.  Both synchronise. */
+ * X, y, the folds, the Gaussian noise scale and the prior scales); the
+ * context takes the checkpoint's step size and inverse mass, whatever it
+ * was created with.  Because every random number is keyed by (seed, chain,
+ * transition), the resumed run continues exactly as the original would
+ * have.  Errors: PCV_ERR_INVALID_ARG for an unwritable or unreadable path,
+ * a file of another run or target, or a truncated or corrupted file (the
+ * ctx is unchanged then); PCV_ERR_DEVICE.  Both synchronise. */
 pcv_status pcv_save(pcv_ctx ctx, const char* path);
 pcv_status pcv_load(pcv_ctx ctx, const char* path);
 

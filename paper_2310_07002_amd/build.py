@@ -16,26 +16,35 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpcv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["api.hip", "k_common.hip", "k_valu.hip", "k_mfma.hip", "posthoc.hip"]
+# (source, extra flags, object name).  The VALU kernels are templates over
+# the arithmetic type and the family; k_valu.hip is compiled once per pair
+# (each instance emits one pair's kernels) and once more for the dispatchers,
+# so the long device compilations run in parallel.
+_VALU_INST = [("k_valu.hip", [f"-DPCV_VALU_T={t}", f"-DPCV_VALU_FAM={fam}"], f"k_valu_{t}_{fam}.o")
+              for t in ("double", "float") for fam in range(4)]
+SOURCES = [("api.hip", [], "api.o"), ("k_common.hip", [], "k_common.o"), ("k_valu.hip", [], "k_valu.o"),
+           ("k_mfma.hip", [], "k_mfma.o"), ("posthoc.hip", [], "posthoc.o")] + _VALU_INST
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed fp32 instructions in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, src + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, extra, name = job
+    obj = os.path.join(BUILD_DIR, name)
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for " + src)
+        raise RuntimeError("hipcc failed for " + src + " " + " ".join(extra))
     return obj
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 4, 16))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,

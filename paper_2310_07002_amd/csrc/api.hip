@@ -659,6 +659,10 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     }
   }
   ctx->prior_const = prior_const;
+  // the target density belongs to the checkpoint fingerprint too: a run
+  // resumes only under the same noise scale and prior
+  ctx->fingerprint = fp_mix(ctx->fingerprint, &m.sigma, sizeof(double));
+  ctx->fingerprint = fp_mix(ctx->fingerprint, prior_prec.data(), sizeof(double) * static_cast<size_t>(d));
 
   // ---- device data -------------------------------------------------------
   double *X64, *y64, *minv, *pprec, *rowc, *fconst;
@@ -1206,13 +1210,13 @@ struct CkptHeader {
   uint64_t payload_hash;
 };
 static_assert(sizeof(CkptHeader) == 160, "checkpoint header has no padding");
-constexpr char kCkptMagic[8] = {'P', 'C', 'V', 'C', 'K', 'P', 'T', '1'};
+constexpr char kCkptMagic[8] = {'P', 'C', 'V', 'C', 'K', 'P', 'T', '2'};
 
 CkptHeader ckpt_header_of(pcv_ctx ctx) {
   const DevModel& m = ctx->m;
   CkptHeader h{};
   std::memcpy(h.magic, kCkptMagic, 8);
-  h.version = 1;
+  h.version = 2;
   h.family = m.family;
   h.precision = ctx->prec;
   h.fold_kind = m.fold_kind;
@@ -1247,10 +1251,13 @@ std::vector<CkptArray> ckpt_arrays(pcv_ctx ctx) {
   const DevModel& m = ctx->m;
   const size_t C = m.C, dC = static_cast<size_t>(m.d) * m.C, DC = static_cast<size_t>(m.D) * m.C;
   const size_t K = static_cast<size_t>(m.KP);
+  // the inverse mass is sampler state (pcv_adapt rewrites it); the step size
+  // travels in the header
   std::vector<CkptArray> a = {{m.q0, 8 * dC},  {m.g0, 8 * dC},  {m.logp0, 8 * C}, {m.s0, 8 * C},
                               {m.Z, 8 * C},    {m.U, 8 * C},    {m.U2, 8 * C},    {m.V, 8 * C},
                               {m.V2, 8 * C},   {m.bmean, 8 * DC}, {m.bm2, 8 * DC}, {m.nacc, 8 * C},
-                              {m.ndiv, 8 * C}, {m.wsum, 8 * C}, {m.center, 8 * K}};
+                              {m.ndiv, 8 * C}, {m.wsum, 8 * C}, {m.center, 8 * K},
+                              {const_cast<double*>(m.minv), 8 * static_cast<size_t>(m.d)}};
   const size_t Lnnz = static_cast<size_t>(m.L) * ctx->test_ptr_host[m.K];
   if (m.hs1) a.push_back({m.hs1, 8 * C});
   if (m.hs2) a.push_back({m.hs2, 8 * Lnnz});
@@ -1315,10 +1322,11 @@ pcv_status pcv_load(pcv_ctx ctx, const char* path) {
     body = std::fread(payload.data(), 1, total, f) == total && std::fgetc(f) == EOF;
   }
   std::fclose(f);
-  if (!got || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+  if (!got || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 2)
     return fail(ctx, PCV_ERR_INVALID_ARG, "not a checkpoint of this library");
   CkptHeader want = ckpt_header_of(ctx);
   want.t = h.t;
+  want.eps = h.eps;   // tuning state, restored below
   want.payload_bytes = h.payload_bytes;
   want.payload_hash = h.payload_hash;
   if (std::memcmp(&want, &h, sizeof(h)) != 0)
@@ -1326,6 +1334,16 @@ pcv_status pcv_load(pcv_ctx ctx, const char* path) {
   if (!body || fp_mix(0xcbf29ce484222325ULL, payload.data(), total) != h.payload_hash)
     return fail(ctx, PCV_ERR_INVALID_ARG, "checkpoint is truncated or corrupted");
   if (h.t < 0 || h.t > 0xFFFFFFFFLL) return fail(ctx, PCV_ERR_INVALID_ARG, "checkpoint iteration out of range");
+  if (!(h.eps > 0) || !std::isfinite(h.eps)) return fail(ctx, PCV_ERR_INVALID_ARG, "checkpoint step size invalid");
+  {
+    // the inverse mass sits last in the payload: it must be positive
+    const size_t off_minv = total - 8 * static_cast<size_t>(ctx->m.d);
+    for (int64_t j = 0; j < ctx->m.d; ++j) {
+      double v;
+      std::memcpy(&v, payload.data() + off_minv + 8 * j, 8);
+      if (!(v > 0) || !std::isfinite(v)) return fail(ctx, PCV_ERR_INVALID_ARG, "checkpoint inverse mass invalid");
+    }
+  }
   CK(hipStreamSynchronize(ctx->st));
   size_t off = 0;
   for (const CkptArray& a : arrs) {
@@ -1333,6 +1351,10 @@ pcv_status pcv_load(pcv_ctx ctx, const char* path) {
     off += a.bytes;
   }
   ctx->t = h.t;
+  if (h.eps != ctx->m.eps) {
+    ctx->m.eps = h.eps;
+    drop_graph(ctx);   // a captured transition holds the old step size
+  }
   return PCV_OK;
 }
 

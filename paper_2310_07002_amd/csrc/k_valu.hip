@@ -412,6 +412,7 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_part(ValuArgs a) {
   }
 }
 
+#if !defined(PCV_VALU_T)
 // Hierarchical family, row splits: one thread per (entry, chain) of the
 // [split][d][C] partials.  Coefficients, mu and log tau add every split,
 // group g the splits that span it (gsplit), in split order; then the prior
@@ -481,9 +482,11 @@ int valu_pb(int64_t p, bool fp64) {
   if (p <= 8) return 8;
   if (p <= 16) return 16;
   if (p <= 32) return 32;
-  if (!fp64 && p <= 64) return 64;
+  if (p <= 64) return 64;
+  (void)fp64;
   return 0;
 }
+#endif
 
 template <typename T, int FAM, int PB>
 static hipError_t launch_mode(const ValuArgs& a, int W, hipStream_t st, size_t smem, int nblk, int ns = 1) {
@@ -499,18 +502,53 @@ static hipError_t launch_mode(const ValuArgs& a, int W, hipStream_t st, size_t s
 }
 
 template <typename T, int FAM>
-static hipError_t launch_fam(const ValuArgs& a, int pb, int W, hipStream_t st, size_t smem, int nblk, int ns = 1) {
+hipError_t launch_fam(const ValuArgs& a, int pb, int W, hipStream_t st, size_t smem, int nblk, int ns) {
   switch (pb) {
     case 4: return launch_mode<T, FAM, 4>(a, W, st, smem, nblk, ns);
     case 8: return launch_mode<T, FAM, 8>(a, W, st, smem, nblk, ns);
     case 16: return launch_mode<T, FAM, 16>(a, W, st, smem, nblk, ns);
     case 32: return launch_mode<T, FAM, 32>(a, W, st, smem, nblk, ns);
-    case 64:
-      if constexpr (sizeof(T) == 4) return launch_mode<T, FAM, 64>(a, W, st, smem, nblk, ns);
-      return hipErrorInvalidValue;
+    case 64: return launch_mode<T, FAM, 64>(a, W, st, smem, nblk, ns);
   }
   return hipErrorInvalidValue;
 }
+
+// Workgroups of k_valu_part per compute unit (registers, LDS and threads),
+// from the runtime's occupancy calculator; 0 if unknown.
+template <typename T, int FAM>
+int part_occupancy_fam(int pb, int W, size_t smem) {
+  const void* f = nullptr;
+  switch (pb) {
+    case 4: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 4>); break;
+    case 8: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 8>); break;
+    case 16: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 16>); break;
+    case 32: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 32>); break;
+    case 64: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 64>); break;
+  }
+  int nb = 0;
+  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * W, smem) != hipSuccess) return 0;
+  return nb;
+}
+
+#if defined(PCV_VALU_T)
+// This translation unit instantiates the kernels of one (arithmetic type,
+// family) pair; the build compiles the file once per pair, in parallel.
+template hipError_t launch_fam<PCV_VALU_T, PCV_VALU_FAM>(const ValuArgs&, int, int, hipStream_t, size_t, int, int);
+template int part_occupancy_fam<PCV_VALU_T, PCV_VALU_FAM>(int, int, size_t);
+}  // namespace pcv
+#else
+#define PCV_VALU_EXTERN(T, F)                                                                                 \
+  extern template hipError_t launch_fam<T, F>(const ValuArgs&, int, int, hipStream_t, size_t, int, int); \
+  extern template int part_occupancy_fam<T, F>(int, int, size_t);
+PCV_VALU_EXTERN(double, FAM_GAUSS)
+PCV_VALU_EXTERN(double, FAM_LOGIT)
+PCV_VALU_EXTERN(double, FAM_POIS)
+PCV_VALU_EXTERN(double, FAM_HIER)
+PCV_VALU_EXTERN(float, FAM_GAUSS)
+PCV_VALU_EXTERN(float, FAM_LOGIT)
+PCV_VALU_EXTERN(float, FAM_POIS)
+PCV_VALU_EXTERN(float, FAM_HIER)
+#undef PCV_VALU_EXTERN
 
 hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int mode, int64_t t0,
                        int n_iter, int n_steps, hipStream_t st) {
@@ -525,17 +563,17 @@ hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int
   const size_t smem = valu_smem_bytes(fp64, W, m.family, m.n_groups, pb);
   if (fp64) {
     switch (m.family) {
-      case FAM_GAUSS: return launch_fam<double, FAM_GAUSS>(a, pb, W, st, smem, nblk);
-      case FAM_LOGIT: return launch_fam<double, FAM_LOGIT>(a, pb, W, st, smem, nblk);
-      case FAM_POIS: return launch_fam<double, FAM_POIS>(a, pb, W, st, smem, nblk);
-      case FAM_HIER: return launch_fam<double, FAM_HIER>(a, pb, W, st, smem, nblk);
+      case FAM_GAUSS: return launch_fam<double, FAM_GAUSS>(a, pb, W, st, smem, nblk, 1);
+      case FAM_LOGIT: return launch_fam<double, FAM_LOGIT>(a, pb, W, st, smem, nblk, 1);
+      case FAM_POIS: return launch_fam<double, FAM_POIS>(a, pb, W, st, smem, nblk, 1);
+      case FAM_HIER: return launch_fam<double, FAM_HIER>(a, pb, W, st, smem, nblk, 1);
     }
   } else {
     switch (m.family) {
-      case FAM_GAUSS: return launch_fam<float, FAM_GAUSS>(a, pb, W, st, smem, nblk);
-      case FAM_LOGIT: return launch_fam<float, FAM_LOGIT>(a, pb, W, st, smem, nblk);
-      case FAM_POIS: return launch_fam<float, FAM_POIS>(a, pb, W, st, smem, nblk);
-      case FAM_HIER: return launch_fam<float, FAM_HIER>(a, pb, W, st, smem, nblk);
+      case FAM_GAUSS: return launch_fam<float, FAM_GAUSS>(a, pb, W, st, smem, nblk, 1);
+      case FAM_LOGIT: return launch_fam<float, FAM_LOGIT>(a, pb, W, st, smem, nblk, 1);
+      case FAM_POIS: return launch_fam<float, FAM_POIS>(a, pb, W, st, smem, nblk, 1);
+      case FAM_HIER: return launch_fam<float, FAM_HIER>(a, pb, W, st, smem, nblk, 1);
     }
   }
   return hipErrorInvalidValue;
@@ -571,25 +609,6 @@ hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb
   return hipErrorInvalidValue;
 }
 
-// Workgroups of k_valu_part per compute unit (registers, LDS and threads),
-// from the runtime's occupancy calculator; 0 if unknown.
-template <typename T, int FAM>
-static int part_occupancy_fam(int pb, int W, size_t smem) {
-  const void* f = nullptr;
-  switch (pb) {
-    case 4: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 4>); break;
-    case 8: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 8>); break;
-    case 16: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 16>); break;
-    case 32: f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 32>); break;
-    case 64:
-      if constexpr (sizeof(T) == 4) f = reinterpret_cast<const void*>(&k_valu_part<T, FAM, 64>);
-      break;
-  }
-  int nb = 0;
-  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * W, smem) != hipSuccess) return 0;
-  return nb;
-}
-
 int valu_part_occupancy(bool fp64, int family, int pb, int W, size_t smem) {
   switch (family) {
     case FAM_GAUSS: return fp64 ? part_occupancy_fam<double, FAM_GAUSS>(pb, W, smem) : part_occupancy_fam<float, FAM_GAUSS>(pb, W, smem);
@@ -609,3 +628,4 @@ hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, const doub
 }
 
 }  // namespace pcv
+#endif
