@@ -56,8 +56,8 @@ enum {
 /* Arithmetic of the log-density / gradient contractions.  Metropolis
  * energies, log predictive draws and all accumulators are fp64 always. */
 enum {
-  PCV_PREC_FP64 = 0,          /* fused fp64 VALU kernel (p <= 32)                   */
-  PCV_PREC_FP32 = 1,          /* fused fp32 VALU kernel (p <= 64)                   */
+  PCV_PREC_FP64 = 0,          /* fp64 VALU kernels (p <= 64)                        */
+  PCV_PREC_FP32 = 1,          /* fp32 VALU kernels (p <= 64)                        */
   PCV_PREC_BF16X3 = 2,        /* bf16 MFMA, X and theta split hi+lo, 3 products each
                                  way, fp32 accumulation (p = 64 or 128)             */
   PCV_PREC_BF16X5 = 3,        /* as BF16X3 with a three-term theta split in the

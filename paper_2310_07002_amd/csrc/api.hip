@@ -603,7 +603,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     ctx->path = PATH_VALU;
     ctx->fp64 = md->precision == PCV_PREC_FP64;
     ctx->pb = valu_pb(p, ctx->fp64);
-    if (!ctx->pb) return fail(ctx, PCV_ERR_UNSUPPORTED, "fused VALU path supports p <= 32 (fp64) or p <= 64 (fp32)");
+    if (!ctx->pb) return fail(ctx, PCV_ERR_UNSUPPORTED, "VALU paths support p <= 64");
     // few chains and many rows: split rows across workgroups (partial sums
     // reduced per leapfrog step) instead of one fused workgroup per 64 chains
     const int64_t chain_blocks = (C + 63) / 64;

@@ -4,7 +4,7 @@
 // accumulation -- without any grid-wide synchronisation, because chains never
 // interact (Section 3.3).  The W waves of the workgroup split the rows; each
 // row of X is read once per wave with scalar loads and broadcast to the 64
-// chains.  Used for narrow designs (p <= 32 in fp64, p <= 64 in fp32).
+// chains.  Used for narrow designs (p <= 64).
 #include <type_traits>
 
 #include "pcv_internal.h"

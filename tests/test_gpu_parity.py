@@ -72,6 +72,7 @@ CASES = [
     ("c3", "fp64", (0, 40), 1e-12, 1e-12),
     ("c2", "fp32", None, 1e-5, 1e-5),
     ("c4", "fp64u", (0, 16), 1e-12, 1e-12),
+    ("c4", "fp64", (0, 16), 1e-12, 1e-12),
     ("c4", "bf16x5", (0, 16), 1e-5, 1e-5),
     ("c4", "bf16x3", (0, 16), 1e-5, 5e-5),
     ("c4", "fp32", (0, 16), 1e-5, 1e-5),
@@ -202,6 +203,8 @@ def test_dense_fold_encoding_matches_index(dev):
 # ---------------------------------------------------------------- single leapfrog trajectories
 
 @pytest.mark.parametrize("name,prec,folds_,tol", [("c1", "fp64", None, 1e-12), ("c3", "fp64", (0, 30), 1e-12),
+                                                 ("c2", "fp32", (0, 10), 1e-5),
+                                                 ("c4", "fp64", (0, 16), 1e-12),
                                                  ("c4", "bf16x3", (0, 16), 1e-5),
                                                  ("c5", "bf16x3", (0, 32), 1e-5),
                                                  ("c5", "bf16x5", (0, 32), 1e-5)])
@@ -418,10 +421,22 @@ def test_loo_elpd_within_mcse_of_closed_form(dev):
     assert d["n_draws"] == w.n_samples
 
 
-def test_autograd_function_matches_finite_differences(dev):
+@pytest.mark.parametrize("name,prec,folds_", [("c1", "fp64", (0, 8)), ("c3", "fp64", (0, 16)),
+                                              ("c4", "fp64", (0, 4)), ("c4", "fp64u", (0, 4)),
+                                              ("c2", "fp64", (0, 3))])
+def test_autograd_function_matches_finite_differences(dev, name, prec, folds_):
+    """PCVLogDensity's backward is the hand-written adjoint: against central
+    differences (h = 1e-6) of the same kernel's fp64 log density on every
+    fp64 path -- the fused VALU kernel (c1), the row-split VALU kernel for
+    interval folds (c3), for the Poisson GLM at p = 64 (c4) and for the
+    hierarchical family (c2, the groups' chain rule), and the plain
+    library-GEMM path.  A central difference of a smooth f errs by about
+    h^2/6 times its third derivative plus 2^-52 |f| / h of rounding; with
+    |log pi| <= 3e4 here that is below 2e-4 absolute."""
     from paper_2310_07002_amd.autograd import log_density
-    w = W.fold_subset(W.make("c4"), 0, 4)
-    s = binding.PCV.from_workload(w, precision=W.PREC_FP64_UNFUSED)
+    w = W.fold_subset(W.make(name), *folds_)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    _say(f"[autograd FD] {name} {prec} C={w.C} d={w.d}")
     theta = torch.tensor(_theta_near_init(w, seed=9), device=dev, requires_grad=True)
     weights = torch.linspace(0.5, 1.5, w.C, dtype=torch.float64, device=dev)
     (log_density(theta, s) * weights).sum().backward()
@@ -429,13 +444,35 @@ def test_autograd_function_matches_finite_differences(dev):
     h = 1e-6
     th = theta.detach().cpu().numpy()
     rng = np.random.default_rng(1)
-    for j in rng.choice(w.d, size=6, replace=False):
+    for j in sorted(rng.choice(w.d, size=min(6, w.d), replace=False).tolist()) + [w.d - 1]:
         e = np.zeros_like(th)
         e[:, j] = h
         lp_p, _ = s.logdensity_grad(torch.tensor(th + e, device=dev), want_grad=False)
         lp_m, _ = s.logdensity_grad(torch.tensor(th - e, device=dev), want_grad=False)
         fd = (lp_p - lp_m).cpu().numpy() / (2 * h) * weights.cpu().numpy()
-        np.testing.assert_allclose(g[:, j], fd, rtol=2e-5, atol=2e-4)
+        np.testing.assert_allclose(g[:, j], fd, rtol=2e-5, atol=2e-4, err_msg=f"coordinate {j}")
+
+
+@pytest.mark.parametrize("name,prec,folds_,tol", [("c4", "bf16x5", (0, 16), 1e-5), ("c4", "bf16x3", (0, 16), 5e-5),
+                                                 ("c5", "bf16x3", (0, 8), 5e-5), ("c2", "fp32", (0, 4), 1e-5)])
+def test_autograd_function_matches_fp64_reference(dev, name, prec, folds_, tol):
+    """PCVLogDensity over the split-precision matrix-core adjoint and the fp32
+    VALU adjoint: the backward (weighted by grad_out) equals the fp64
+    oracle's gradient at the normwise tolerance stated for each precision."""
+    from paper_2310_07002_amd.autograd import log_density
+    w = W.fold_subset(W.make(name), *folds_)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    th = _theta_near_init(w, seed=12)
+    theta = torch.tensor(th, device=dev, requires_grad=True)
+    weights = torch.linspace(0.5, 1.5, w.C, dtype=torch.float64, device=dev)
+    lp = log_density(theta, s)
+    (lp * weights).sum().backward()
+    lp_o, g_o = _oracle_eval(w, th)
+    wv = weights.cpu().numpy()[:, None]
+    err = _normwise(theta.grad.cpu().numpy(), wv * g_o)
+    _say(f"[autograd ref] {name} {prec}: grad normwise max {err.max():.2e}")
+    assert err.max() < tol
+    assert (np.abs(lp.detach().cpu().numpy() - lp_o) / np.abs(lp_o)).max() < 1e-5
 
 
 def test_state_roundtrip_and_divergence_counting(dev):
@@ -545,6 +582,35 @@ def test_checkpoint_resume_is_exact(dev, tmp_path, name, prec, folds_, mode):
         b.load(short)
     b.step(1)                                   # still usable after refused loads
     assert b.diagnostics()["n_iter"] == 56
+
+
+def test_checkpoint_guards_the_target_and_carries_the_tuning(dev, tmp_path):
+    """A checkpoint is refused by a context whose target differs (noise scale
+    or prior scales), and it carries the step size and inverse mass that
+    window adaptation left: a fresh context created with the unadapted
+    tuning resumes a post-adaptation checkpoint bit for bit."""
+    w = dataclasses.replace(W.fold_subset(W.make("c1"), 0, 12), n_warmup=10)
+    path = str(tmp_path / "t.ckpt")
+    a = binding.PCV.from_workload(w)
+    a.step(12)
+    a.save(path)
+    for other in (dataclasses.replace(w, sigma=w.sigma * 1.25),
+                  dataclasses.replace(w, prior_scale=w.prior_scale * 2.0)):
+        with pytest.raises(binding.PcvError, match="another"):
+            binding.PCV.from_workload(other).load(path)
+    f = W.full_data(W.make("c1"), L=8, n_warmup=400)
+    x = binding.PCV.from_workload(f, precision=W.PREC_FP64)
+    r = x.adapt(150, 0.8)
+    assert r["step_size"] != f.step_size
+    x.step(5)
+    x.save(path)
+    x.step(20)
+    y = binding.PCV.from_workload(f, precision=W.PREC_FP64)     # created with the unadapted tuning
+    y.load(path)
+    y.step(20)
+    for u, v in zip(x.get_state(), y.get_state()):
+        np.testing.assert_array_equal(u, v)
+    _say(f"[checkpoint] adapted eps {r['step_size']:.4f} resumed bit for bit")
 
 
 @pytest.mark.parametrize("name,prec,tol_g", [("c5", "bf16x3", 5e-5), ("c4", "bf16x3", 5e-5), ("c5", "bf16x5", 1e-5)])
