@@ -250,6 +250,28 @@ pcv_status pcv_elpd_model(pcv_ctx ctx, int32_t model, double* elpd, double* mcse
 pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* rhat_max_rep,
                                  double* rhat_rep);
 
+/* Size, in doubles, of the static device scratch array that
+ * pcv_shuffle_benchmark_noalloc uses (8 MiB).  Each GPU the library runs on
+ * holds one copy from the first pcv_init on that device until the process
+ * ends. */
+#define PCV_SHUFFLE_NOALLOC_MAX_DOUBLES (1 << 20)
+
+/* pcv_shuffle_benchmark for callers that cannot allocate device memory:
+ * monitoring loops that re-run the benchmark at every batch end, serving
+ * loops and harnesses that forbid hipMalloc.  Same arguments, same kernels
+ * and bit-identical results; the replicate buffers (M*K*R + R doubles, M*K
+ * the run's posteriors) live in the library's static scratch array of this
+ * GPU instead of fresh allocations, and the call makes no hipMalloc, hipFree
+ * or other allocating call.  The kernels overwrite the buffers in full, so
+ * nothing carries over from earlier calls; but every context on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other streams
+ * or threads) race: the caller must serialise them.  Synchronises.
+ * Errors: those of pcv_shuffle_benchmark, plus PCV_ERR_INVALID_ARG, before
+ * any device work, when (M*K + 1) * R exceeds
+ * PCV_SHUFFLE_NOALLOC_MAX_DOUBLES. */
+pcv_status pcv_shuffle_benchmark_noalloc(pcv_ctx ctx, int32_t R, uint64_t seed, double* rhat_max_rep,
+                                         double* rhat_rep);
+
 /* Hyvarinen (HS) and Dawid-Sebastiani (DSS) cross-validation scores
  * (Appendix, sections HS and DSS; positively oriented), summed over folds
  * and per fold (K entries each; any output may be NULL).  Per fold k with

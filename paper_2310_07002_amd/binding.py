@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "PCV_OK", 1: "PCV_ERR_INVALID_ARG", 2: "PCV_ERR_NOMEM", 3: "P
                 4: "PCV_ERR_STATE", 5: "PCV_ERR_UNSUPPORTED"}
 
 EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_elpd",
-            "pcv_shuffle_benchmark", "pcv_scores", "pcv_get_draws", "pcv_posthoc", "pcv_compare",
+            "pcv_shuffle_benchmark", "pcv_shuffle_benchmark_noalloc", "pcv_scores", "pcv_get_draws",
+            "pcv_posthoc", "pcv_compare",
             "pcv_destroy", "pcv_last_error", "pcv_status_str",
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
             "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
@@ -110,6 +111,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_diagnostics": ([P, ctypes.POINTER(pcv_diag)], I32),
         "pcv_elpd": ([P, dp, dp, dp, dp], I32),
         "pcv_shuffle_benchmark": ([P, I32, U64, dp, dp], I32),
+        "pcv_shuffle_benchmark_noalloc": ([P, I32, U64, dp, dp], I32),
         "pcv_compare": ([P, P, ctypes.POINTER(pcv_comparison)], I32),
         "pcv_scores": ([P, dp, dp, dp, dp], I32),
         "pcv_get_draws": ([P, dp, I64, ctypes.POINTER(I64)], I32),
@@ -344,6 +346,15 @@ class PCV:
         rep = np.zeros(self.M * self.K * R) if per_fold else None
         self._check(self._lib.pcv_shuffle_benchmark(self._ctx, R, seed, _dptr(mx), _dptr(rep)),
                     "pcv_shuffle_benchmark")
+        return (mx, rep.reshape(self.M * self.K, R)) if per_fold else mx
+
+    def shuffle_benchmark_noalloc(self, R: int, seed: int, per_fold: bool = False):
+        """The same benchmark on the library's static device scratch (no
+        device allocation; at most PCV_SHUFFLE_NOALLOC_MAX_DOUBLES doubles)."""
+        mx = np.zeros(R)
+        rep = np.zeros(self.M * self.K * R) if per_fold else None
+        self._check(self._lib.pcv_shuffle_benchmark_noalloc(self._ctx, R, seed, _dptr(mx), _dptr(rep)),
+                    "pcv_shuffle_benchmark_noalloc")
         return (mx, rep.reshape(self.M * self.K, R)) if per_fold else mx
 
     def logdensity_grad(self, theta, want_grad: bool = True):

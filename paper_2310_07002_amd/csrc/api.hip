@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -105,6 +106,7 @@ struct pcv_ctx_s {
   std::vector<int32_t> group_of_host;   // row-split VALU, hierarchical: groups of the rows
   std::vector<int32_t> test_ptr_host;   // [K+1] test rows of each fold (CSR)
   std::vector<int64_t> sq_ptr_host;     // [K+1] prefix sums of squared test-set sizes
+  double* noalloc_scratch = nullptr;    // this device's copy of the static scratch array
 };
 
 namespace {
@@ -444,6 +446,36 @@ void pcv_destroy(pcv_ctx ctx) {
   delete ctx;
 }
 
+// Scratch memory of pcv_shuffle_benchmark_noalloc: a file-scope device
+// array, so that entry point allocates nothing.  Every GPU the library runs
+// on holds its own copy until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: the device address
+// of this GPU's copy is looked up once per device (with that device
+// current) and kept in g_scratch_dev, and only that address reaches kernels.
+static __device__ __align__(256) double scratch[PCV_SHUFFLE_NOALLOC_MAX_DOUBLES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;   // [device] address of its copy, or null
+
+// Resolve (once per device) the current device's copy of the scratch array.
+pcv_status resolve_scratch(pcv_ctx ctx) {
+  int dev = 0;
+  CK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (static_cast<size_t>(dev) >= g_scratch_dev.size()) g_scratch_dev.resize(static_cast<size_t>(dev) + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(ctx, PCV_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  ctx->noalloc_scratch = g_scratch_dev[dev];
+  return PCV_OK;
+}
+}  // namespace
+
 static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, const double* y,
                             const pcv_folds* fm) {
   if (!md || !X || !y || !fm) return fail(ctx, PCV_ERR_INVALID_ARG, "null argument");
@@ -666,6 +698,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
 
   // ---- device data -------------------------------------------------------
   double *X64, *y64, *minv, *pprec, *rowc, *fconst;
+  // first device work: everything above only validated the host arguments
+  TRY(resolve_scratch(ctx));
   TRY(upload(ctx, &X64, X, n * p));
   TRY(upload(ctx, &y64, y, n));
   TRY(upload(ctx, &minv, md->inv_mass, d));
@@ -1071,11 +1105,35 @@ pcv_status pcv_elpd(pcv_ctx ctx, double* elpd, double* mcse, double* elpd_fold, 
   return PCV_OK;
 }
 
+// Block-shuffle replicates into device buffers rep (KP*R) and mx (R), both
+// written in full by the kernels, then to the caller's host arrays.
+static pcv_status shuffle_run(pcv_ctx ctx, int64_t N, int32_t R, uint64_t seed, double* rep, double* mx,
+                              double* rhat_max_rep, double* rhat_rep) {
+  const size_t nrep = static_cast<size_t>(ctx->m.KP) * R;
+  hipError_t e = launch_shuffle(ctx->m, N, R, static_cast<uint32_t>(seed & 0xFFFFFFFFu),
+                                static_cast<uint32_t>(seed >> 32), rep, mx, ctx->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(rhat_max_rep, mx, sizeof(double) * R, hipMemcpyDeviceToHost, ctx->st);
+  if (e == hipSuccess && rhat_rep)
+    e = hipMemcpyAsync(rhat_rep, rep, sizeof(double) * nrep, hipMemcpyDeviceToHost, ctx->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+  if (e != hipSuccess) {
+    ctx->dead = true;
+    return fail(ctx, PCV_ERR_DEVICE, hipGetErrorString(e));
+  }
+  return PCV_OK;
+}
+
+static pcv_status shuffle_check(pcv_ctx ctx, int32_t R, const double* rhat_max_rep, int64_t* N) {
+  if (R < 1 || !rhat_max_rep) return fail(ctx, PCV_ERR_INVALID_ARG, "R >= 1 and an output buffer are required");
+  *N = std::max<int64_t>(0, ctx->t - ctx->m.n_warmup);
+  if (*N < 2) return fail(ctx, PCV_ERR_STATE, "fewer than 2 post-warm-up draws");
+  return PCV_OK;
+}
+
 pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* rhat_max_rep, double* rhat_rep) {
   if (!usable(ctx)) return PCV_ERR_STATE;
-  if (R < 1 || !rhat_max_rep) return fail(ctx, PCV_ERR_INVALID_ARG, "R >= 1 and an output buffer are required");
-  const int64_t N = std::max<int64_t>(0, ctx->t - ctx->m.n_warmup);
-  if (N < 2) return fail(ctx, PCV_ERR_STATE, "fewer than 2 post-warm-up draws");
+  int64_t N = 0;
+  TRY(shuffle_check(ctx, R, rhat_max_rep, &N));
   double *rep, *mx;
   const size_t nrep = static_cast<size_t>(ctx->m.KP) * R;
   if (hipMalloc(&rep, sizeof(double) * nrep) != hipSuccess) return fail(ctx, PCV_ERR_NOMEM, "hipMalloc failed");
@@ -1083,19 +1141,26 @@ pcv_status pcv_shuffle_benchmark(pcv_ctx ctx, int32_t R, uint64_t seed, double* 
     (void)hipFree(rep);
     return fail(ctx, PCV_ERR_NOMEM, "hipMalloc failed");
   }
-  hipError_t e = launch_shuffle(ctx->m, N, R, static_cast<uint32_t>(seed & 0xFFFFFFFFu),
-                                static_cast<uint32_t>(seed >> 32), rep, mx, ctx->st);
-  if (e == hipSuccess) e = hipMemcpyAsync(rhat_max_rep, mx, sizeof(double) * R, hipMemcpyDeviceToHost, ctx->st);
-  if (e == hipSuccess && rhat_rep)
-    e = hipMemcpyAsync(rhat_rep, rep, sizeof(double) * nrep, hipMemcpyDeviceToHost, ctx->st);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->st);
+  const pcv_status s = shuffle_run(ctx, N, R, seed, rep, mx, rhat_max_rep, rhat_rep);
   (void)hipFree(rep);
   (void)hipFree(mx);
-  if (e != hipSuccess) {
-    ctx->dead = true;
-    return fail(ctx, PCV_ERR_DEVICE, hipGetErrorString(e));
-  }
-  return PCV_OK;
+  return s;
+}
+
+pcv_status pcv_shuffle_benchmark_noalloc(pcv_ctx ctx, int32_t R, uint64_t seed, double* rhat_max_rep,
+                                         double* rhat_rep) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  int64_t N = 0;
+  TRY(shuffle_check(ctx, R, rhat_max_rep, &N));
+  const int64_t need = (static_cast<int64_t>(ctx->m.KP) + 1) * R;
+  if (need > PCV_SHUFFLE_NOALLOC_MAX_DOUBLES)
+    return fail(ctx, PCV_ERR_INVALID_ARG,
+                "(K + 1) * R = " + std::to_string(need) + " doubles exceed the static scratch of " +
+                    std::to_string(PCV_SHUFFLE_NOALLOC_MAX_DOUBLES) + " (use pcv_shuffle_benchmark)");
+  if (!ctx->noalloc_scratch) return fail(ctx, PCV_ERR_STATE, "the scratch array of this device was not resolved");
+  double* rep = ctx->noalloc_scratch;
+  double* mx = rep + static_cast<int64_t>(ctx->m.KP) * R;
+  return shuffle_run(ctx, N, R, seed, rep, mx, rhat_max_rep, rhat_rep);
 }
 
 pcv_status pcv_logdensity_grad(pcv_ctx ctx, const double* theta_dev, double* logp_dev, double* grad_dev,
