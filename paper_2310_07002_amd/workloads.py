@@ -17,6 +17,10 @@ for them:
       -- time-series blocked CV as in the air-passenger example
   c4  K-fold CV of a Poisson log-link GLM (n=20000, p=64, K=500, L=8)
   c5  blocked CV of a logistic GLM (n=100000, p=128, K=10000, L=4)
+  ex1 the paper's Example 1: LOGO-CV of a grouped Gaussian regression with
+      hierarchical intercepts and unknown noise scale (J=50 groups of 5 rows,
+      4 group-level covariates, K=50, L=4), model A (all covariates) against
+      model B (one dropped)
 
 Settings the paper leaves open (step size, mass matrix, warm-up length, the
 full-data fit that seeds the chains) are fixed here; the reasoning for each is
@@ -40,6 +44,8 @@ GAUSSIAN = 0
 LOGISTIC = 1
 POISSON = 2
 HIER_LOGISTIC = 3
+HIER_GAUSSIAN = 4
+HIER_FAMILIES = (HIER_LOGISTIC, HIER_GAUSSIAN)
 
 # Arithmetic used by the GPU path for the contractions.
 PREC_FP64 = 0
@@ -73,7 +79,7 @@ class Workload:
     fold_index: Optional[np.ndarray] = None   # [n] int32 (INDEX)
     intervals: Optional[np.ndarray] = None    # [K, 4] int64 (INTERVALS)
     roles: Optional[np.ndarray] = None        # [K, n] int8 (DENSE)
-    group_of: Optional[np.ndarray] = None     # [n] int32 (HIER_LOGISTIC)
+    group_of: Optional[np.ndarray] = None     # [n] int32 (hierarchical families)
     n_groups: int = 0
     sigma: float = 1.0
     prior_scale: Optional[np.ndarray] = None  # [d]
@@ -108,6 +114,8 @@ class Workload:
     def d(self) -> int:
         if self.family == HIER_LOGISTIC:
             return self.p + 2 + self.n_groups
+        if self.family == HIER_GAUSSIAN:
+            return self.p + 3 + self.n_groups
         return self.p
 
     @property
@@ -242,6 +250,71 @@ def make_c2(seed_offset: int = 2) -> Workload:
         n_blocks=5, seed=seed + 1, truth=truth)
 
 
+EX1_SCALE_VAR = 10.0    # variance of N(0, 10) designs and of the half-normal scale priors
+
+
+def make_ex1(seed_offset: int = 6, J: int = 50, Nj: int = 5) -> Workload:
+    """Example 1 (Section 2): grouped Gaussian regression, LOGO-CV.
+
+    J = 50 groups of N_j = 5 rows; the J x 4 group-level design has N(0, 10)
+    entries and row i of group j carries x_j.  True values are drawn from the
+    priors: beta ~ N(0, I), mu ~ N(0, 1), sigma_a and sigma_y half-normal with
+    variance 10, alpha_j ~ N(mu, sigma_a^2); y_ij ~ N(alpha_j + x_j'beta,
+    sigma_y^2).  theta = [beta (4), mu, log sigma_a, log sigma_y, z (J)] with
+    alpha_j = mu + sigma_a z_j.  K = J folds, L = 4 chains.  (J and Nj other
+    than 50 and 5 give larger instances of the same model.)
+    """
+    seed = DATA_SEED_BASE + seed_offset
+    rng = np.random.default_rng(seed)
+    p = 4
+    sd = math.sqrt(EX1_SCALE_VAR)
+    Xg = sd * rng.standard_normal((J, p))
+    group_of = np.repeat(np.arange(J, dtype=np.int32), Nj)
+    X = Xg[group_of].copy()
+    n = X.shape[0]
+    beta = rng.standard_normal(p)
+    mu = rng.standard_normal()
+    sig_a = abs(sd * rng.standard_normal())
+    sig_y = abs(sd * rng.standard_normal())
+    z = rng.standard_normal(J)
+    eta = X @ beta + mu + sig_a * z[group_of]
+    y = eta + sig_y * rng.standard_normal(n)
+    d = p + 3 + J
+    truth = np.concatenate([beta, [mu, math.log(sig_a), math.log(sig_y)], z])
+    # Fisher information at the truth (Jacobian of eta wrt theta, Gaussian
+    # weight 1/sigma_y^2; log sigma_y: 2 per row) plus the prior curvature
+    Jm = np.zeros((n, d))
+    Jm[:, :p] = X
+    Jm[:, p] = 1.0
+    Jm[:, p + 1] = sig_a * z[group_of]
+    Jm[np.arange(n), p + 3 + group_of] = sig_a
+    prec = Jm.T @ Jm / sig_y ** 2
+    prec[p + 2, p + 2] = 2.0 * n
+    prior_prec = np.ones(d)
+    prior_prec[p + 1] = 2.0 * sig_a ** 2 / EX1_SCALE_VAR
+    prior_prec[p + 2] = 2.0 * sig_y ** 2 / EX1_SCALE_VAR
+    prec[np.diag_indices(d)] += prior_prec
+    inv_mass = _diag_cov_from_precision(prec)
+    K, L = J, 4
+    init = _init_positions(np.random.default_rng([seed, 1]), truth, inv_mass, K * L)
+    return Workload(
+        name="ex1_logo_hier_gaussian", family=HIER_GAUSSIAN, precision=PREC_FP64, X=X, y=y,
+        K=K, L=L, fold_kind=FOLDS_INDEX, fold_index=group_of.copy(), group_of=group_of,
+        n_groups=J, prior_scale=np.ones(d), step_size=0.25, n_leapfrog=8,
+        inv_mass=inv_mass, init_pos=init, n_warmup=250, n_samples=1000, batch_size=50,
+        n_blocks=5, seed=seed + 1, truth=truth)
+
+
+def make_ex1_ab(seed_offset: int = 6) -> Workload:
+    """Example 1's two models in one launch (Sections 2 and 2.3): model A
+    uses all 4 covariates, model B drops one, the covariate whose true
+    coefficient is largest in magnitude (the paper does not say which)."""
+    w = make_ex1(seed_offset)
+    masks = np.ones((2, w.p), dtype=np.uint8)
+    masks[1, int(np.argmax(np.abs(w.truth[:w.p])))] = 0
+    return with_models(w, masks)
+
+
 AR4_RHO = np.array([0.86, -0.5016, 0.284, -0.1])
 
 
@@ -339,7 +412,8 @@ def make_c5(seed_offset: int = 5) -> Workload:
         x_hi=hi, x_lo=lo)
 
 
-MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5}
+MAKERS = {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c4": make_c4, "c5": make_c5, "ex1": make_ex1,
+          "ex1_ab": lambda: make_ex1_ab()}
 
 
 def make(name: str) -> Workload:
@@ -425,8 +499,10 @@ def drop_covariates(w: Workload, cols, zero: bool = False) -> Workload:
     scales, mass-matrix entries and initial positions of the kept covariates
     are those of the full model.  zero=True keeps p and zeroes the columns
     instead (the masked form of Appendix B: the dropped coefficients remain
-    as parameters the likelihood ignores), for paths built for fixed p."""
-    assert w.family in (GAUSSIAN, LOGISTIC, POISSON), "GLM families only"
+    as parameters the likelihood ignores), for paths built for fixed p; that
+    form also serves the hierarchical Gaussian family."""
+    assert w.family in (GAUSSIAN, LOGISTIC, POISSON) or (zero and w.family == HIER_GAUSSIAN), \
+        "GLM families (and the hierarchical Gaussian with zero=True) only"
     if zero:
         sub = dataclasses.replace(w)
         sub.name = w.name + "_zero_" + "_".join(str(int(c)) for c in np.atleast_1d(cols))

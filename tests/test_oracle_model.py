@@ -62,7 +62,7 @@ def test_loglik_rows_match_library_densities():
 def _small(family, n=40, p=3, K=4, L=2, seed=0, hier_groups=0):
     rng = np.random.default_rng(seed)
     X = rng.normal(size=(n, p))
-    if family == model.GAUSSIAN:
+    if family in (model.GAUSSIAN, model.HIER_GAUSSIAN):
         y = rng.normal(size=n)
     elif family == model.POISSON:
         y = rng.poisson(1.5, size=n).astype(float)
@@ -83,7 +83,8 @@ def _small(family, n=40, p=3, K=4, L=2, seed=0, hier_groups=0):
 
 
 @pytest.mark.parametrize("family,groups", [(model.GAUSSIAN, 0), (model.LOGISTIC, 0),
-                                           (model.POISSON, 0), (model.HIER_LOGISTIC, 5)])
+                                           (model.POISSON, 0), (model.HIER_LOGISTIC, 5),
+                                           (model.HIER_GAUSSIAN, 5)])
 def test_gradient_matches_central_differences(family, groups):
     w = _small(family, hier_groups=groups)
     rng = np.random.default_rng(1)
@@ -136,6 +137,83 @@ def test_hier_prior_is_halfnormal_with_jacobian():
     theta[:, w.p + 1] = u
     lp = model.log_prior(w, theta) - (w.d - 1) * (-0.5 * math.log(2 * math.pi))
     assert abs(np.trapezoid(np.exp(lp), u) - 1.0) < 1e-6
+
+
+def _hier_gauss_by_loops(w, theta, rows):
+    """log prior + sum over `rows` of the row log densities, for one chain,
+    by explicit loops and library densities (Example 1's model as written:
+    alpha_j = mu + sigma_a z_j, y ~ N(alpha_j + x'beta, sigma_y^2), half-normal
+    scale priors with variance 10 in their log-scale parameters)."""
+    p = w.p
+    beta, mu, ua, uy, z = theta[:p], theta[p], theta[p + 1], theta[p + 2], theta[p + 3:]
+    sa, sy = math.exp(ua), math.exp(uy)
+    total = 0.0
+    for i in rows:
+        eta = sum(w.X[i, j] * beta[j] for j in range(p)) + mu + sa * z[w.group_of[i]]
+        total += stats.norm.logpdf(w.y[i], loc=eta, scale=sy)
+    prior = (stats.norm.logpdf(beta).sum() + stats.norm.logpdf(mu) + stats.norm.logpdf(z).sum()
+             + stats.halfnorm.logpdf(sa, scale=math.sqrt(10.0)) + ua
+             + stats.halfnorm.logpdf(sy, scale=math.sqrt(10.0)) + uy)
+    return prior, total
+
+
+def test_hier_gaussian_value_and_predictive_by_loops():
+    """Example 1's family: log density and LOGO log predictive against the
+    model written out with scipy's normal and half-normal densities."""
+    w = _small(model.HIER_GAUSSIAN, n=30, hier_groups=4)
+    rng = np.random.default_rng(5)
+    theta = 0.5 * rng.normal(size=(w.C, w.d))
+    roles = folds.roles_of(w)
+    foc = np.arange(w.C) // w.L
+    lp = model.log_density(w, theta, roles, foc)
+    s = model.log_pred(w, theta, roles, foc)
+    for c in range(w.C):
+        k = foc[c]
+        prior, lik = _hier_gauss_by_loops(w, theta[c], np.flatnonzero(roles[k] == folds.ROLE_TRAIN))
+        _, pred = _hier_gauss_by_loops(w, theta[c], np.flatnonzero(roles[k] == folds.ROLE_TEST))
+        assert abs(lp[c] - (prior + lik)) < 1e-10 * abs(prior + lik)
+        assert abs(s[c] - pred) < 1e-10 * abs(pred)
+
+
+def test_hier_gaussian_gradient_matches_conditional_conjugate_posterior():
+    """At fixed log scales the (beta, mu, z) block of Example 1's model is a
+    linear Gaussian regression y = A (beta, mu, z) + noise, A = [X, 1, sigma_a
+    G] (G the group indicators of the training rows), with an N(0, I) prior:
+    its conditional posterior is N(m, P^-1), P = I + A'A / sigma_y^2,
+    m = P^-1 A'y / sigma_y^2, so the gradient of the log density in that
+    block is -P (theta_lin - m) exactly."""
+    w = _small(model.HIER_GAUSSIAN, n=36, p=3, hier_groups=6)
+    rng = np.random.default_rng(9)
+    roles = folds.roles_of(w)
+    for k in (0, 3):
+        theta = rng.normal(size=(1, w.d))
+        tr = roles[k] == folds.ROLE_TRAIN
+        sa, sy = math.exp(theta[0, w.p + 1]), math.exp(theta[0, w.p + 2])
+        Gm = np.zeros((w.n, w.n_groups))
+        Gm[np.arange(w.n), w.group_of] = 1.0
+        A = np.concatenate([w.X, np.ones((w.n, 1)), sa * Gm], axis=1)[tr]
+        P = np.eye(A.shape[1]) + A.T @ A / sy ** 2
+        m = np.linalg.solve(P, A.T @ w.y[tr] / sy ** 2)
+        lin = np.concatenate([np.arange(w.p + 1), np.arange(w.p + 3, w.d)])
+        g = model.grad_log_density(w, theta, roles, np.array([k]))[0]
+        np.testing.assert_allclose(g[lin], -P @ (theta[0, lin] - m), rtol=1e-10, atol=1e-10)
+
+
+def test_hier_gaussian_scale_priors_are_halfnormal_with_jacobian():
+    """exp of each log-scale's prior part integrates to one over u (the
+    half-normal with variance 10 under sigma = e^u)."""
+    w = _small(model.HIER_GAUSSIAN, hier_groups=2)
+    u = np.linspace(-30, 5, 40001)
+    for j in (w.p + 1, w.p + 2):
+        theta = np.zeros((u.size, w.d))
+        theta[:, w.p + 1] = -40.0
+        theta[:, w.p + 2] = -40.0
+        theta[:, j] = u
+        lp = model.log_prior(w, theta)
+        # subtract the standard-normal block and the other scale's term
+        lp = lp - (w.d - 2) * (-0.5 * math.log(2 * math.pi))
+        lp = lp - (stats.halfnorm.logpdf(math.exp(-40.0), scale=math.sqrt(10.0)) - 40.0)
+        assert abs(np.trapezoid(np.exp(lp), u) - 1.0) < 1e-6, j
 
 
 # --------------------------------------------------------------------------- conjugate case
