@@ -14,8 +14,10 @@
  *    adjacent).  Random streams are keyed by the global chain id
  *    chain_offset + c, so a run over a subset of folds reproduces exactly the
  *    same chains as the full run.
- *  - d = p for the GLM families and p + 2 + n_groups for the hierarchical
- *    logistic family (theta = [beta(p), mu, log tau, z(n_groups)]).
+ *  - d = p for the GLM families, p + 2 + n_groups for the hierarchical
+ *    logistic family (theta = [beta(p), mu, log tau, z(n_groups)]) and
+ *    p + 3 + n_groups for the hierarchical Gaussian family (theta = [beta(p),
+ *    mu, log sigma_a, log sigma_y, z(n_groups)], alpha_g = mu + sigma_a z_g).
  *  - Host arrays passed to pcv_init are copied; the caller may free them on
  *    return.  Device pointers passed to the test hooks are borrowed for the
  *    duration of the call and must be device memory of the current HIP device.
@@ -50,7 +52,10 @@ enum {
   PCV_FAMILY_GAUSSIAN = 0,        /* y ~ N(x'theta, sigma^2), sigma known      */
   PCV_FAMILY_LOGISTIC = 1,        /* y in {0,1}, logit link                   */
   PCV_FAMILY_POISSON = 2,         /* y in {0,1,2,...}, log link               */
-  PCV_FAMILY_HIER_LOGISTIC = 3    /* logit(P(y=1)) = x'beta + mu + tau z_g(n) */
+  PCV_FAMILY_HIER_LOGISTIC = 3,   /* logit(P(y=1)) = x'beta + mu + tau z_g(n) */
+  PCV_FAMILY_HIER_GAUSSIAN = 4    /* y ~ N(x'beta + mu + sigma_a z_g(n), sigma_y^2),
+                                     sigma_y unknown: the grouped regression of
+                                     Section 2, Example 1 (fp64 / fp32 paths)     */
 };
 
 /* Arithmetic of the log-density / gradient contractions.  Metropolis
@@ -120,8 +125,10 @@ typedef struct pcv_model {
   const int32_t* group_of;     /* HIER_LOGISTIC: n entries in [0, n_groups), sorted */
   double sigma;                /* GAUSSIAN: known noise sd                          */
   const double* prior_scale;   /* d entries: theta_j ~ N(0, prior_scale_j^2) (GLMs);
-                                  NULL = all 1.  HIER: beta, mu, z ~ N(0,1),
-                                  tau ~ HalfNormal(1); the array is ignored          */
+                                  NULL = all 1.  HIER_LOGISTIC: beta, mu, z ~ N(0,1),
+                                  tau ~ HalfNormal(1); HIER_GAUSSIAN: beta, mu, z ~
+                                  N(0,1), sigma_a and sigma_y half-normal with
+                                  variance 10 (Example 1); the array is ignored     */
   double step_size;            /* leapfrog step eps (> 0)                            */
   int32_t n_leapfrog;          /* leapfrog steps per transition S (>= 1)             */
   const double* inv_mass;      /* d entries (> 0): diagonal inverse mass matrix      */
@@ -145,7 +152,8 @@ typedef struct pcv_model {
    * then holds M*K posteriors, model-major: chain c = (m*K + k)*L + l is chain
    * l of fold k under model m, so C = M*K*L and init_pos has M*K*L rows; the
    * per-fold arrays of the diagnostics have M*K entries in the same order.
-   * GLM families; not with scores or the plain fp64 path. */
+   * Not with scores or the plain fp64 path; the hierarchical families (masks
+   * on beta) on the fp64 and fp32 paths. */
   int32_t n_models;            /* M (0 or 1: one model, model_mask ignored)          */
   const uint8_t* model_mask;   /* M*p entries, 0 or 1                               */
 } pcv_model;
@@ -388,8 +396,9 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
 
 /* Autotuner for the hot kernel's launch shape.  It times candidate shapes of
  * the gradient kernel:
- * - matrix-core path: the number of row splits per 256-chain tile, around
- *   the analytic choice made at init;
+ * - matrix-core path: the MFMA tile shape (16x16x32 or 32x32x16 bf16
+ *   products) and the number of row splits per 256-chain tile, around the
+ *   analytic choice made at init;
  * - fused VALU path: waves per workgroup, each owning a range of rows.
  * Timing runs on a scratch copy of the current positions, so the chains are
  * untouched.  The fastest shape is kept, and the captured transition graph is
@@ -398,11 +407,22 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
  * family, precision, fold encoding, sizes and GPU architecture.  A hit is
  * applied without timing; a miss is timed and written back (created,
  * updated or extended).
- * config receives the shape (split count or waves); ms receives its mean
- * kernel time (both optional).  Synchronises.
+ * config receives the shape as one integer (matrix-core path:
+ * 256 * tile + splits, tile 0 = 16x16x32 and 1 = 32x32x16 MFMAs; row-split
+ * VALU path: splits; fused VALU path: waves); ms receives its mean kernel
+ * time (both optional).  Synchronises.
  * Errors: PCV_ERR_UNSUPPORTED on the plain fp64 path; PCV_ERR_INVALID_ARG if
  * the cache cannot be written; PCV_ERR_DEVICE. */
 pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, double* ms);
+
+/* Apply, or read, a launch shape in pcv_autotune's encoding (for instance
+ * one tuned elsewhere): the captured transition graph is rebuilt on the next
+ * pcv_step.  Results depend on the shape only through the order of floating
+ * point sums.  Errors: PCV_ERR_INVALID_ARG for a shape out of range for this
+ * context (the context is unchanged); PCV_ERR_UNSUPPORTED on the plain fp64
+ * path. */
+pcv_status pcv_set_launch_config(pcv_ctx ctx, int32_t config);
+pcv_status pcv_get_launch_config(pcv_ctx ctx, int32_t* config);
 
 /* Checkpoint and resume.  pcv_save writes everything a run carries between
  * transitions to the file `path`:

@@ -28,7 +28,7 @@ EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_el
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
             "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
             "pcv_adapt", "pcv_init_positions", "pcv_elpd_model", "pcv_compare_models",
-            "pcv_timing_enable", "pcv_timing_read"]
+            "pcv_timing_enable", "pcv_timing_read", "pcv_set_launch_config", "pcv_get_launch_config"]
 
 
 class PcvError(RuntimeError):
@@ -125,6 +125,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_set_state": ([P, dp], I32),
         "pcv_get_accumulators": ([P, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
         "pcv_autotune": ([P, ctypes.c_char_p, ctypes.POINTER(I32), dp], I32),
+        "pcv_set_launch_config": ([P, I32], I32),
+        "pcv_get_launch_config": ([P, ctypes.POINTER(I32)], I32),
         "pcv_save": ([P, ctypes.c_char_p], I32),
         "pcv_load": ([P, ctypes.c_char_p], I32),
         "pcv_philox": ([U64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, I64,
@@ -207,7 +209,9 @@ class PCV:
         self.M = max(1, int(n_models))
         self.C = self.M * self.K * self.L
         self._scores = int(scores)
-        self.d = p + 2 + n_groups if group_of is not None else p
+        # parameters per chain: GLMs p; hierarchical logistic p + 2 + groups;
+        # hierarchical Gaussian p + 3 + groups (its extra log sigma_y)
+        self.d = p + (3 if family == 4 else 2) + n_groups if group_of is not None else p
         keep = []
 
         def arr(a, dt):
@@ -457,6 +461,15 @@ class PCV:
         self._check(self._lib.pcv_autotune(self._ctx, os.fsencode(cache_path) if cache_path else None,
                                            ctypes.byref(cfg), ctypes.byref(ms)), "pcv_autotune")
         return {"config": cfg.value, "ms": ms.value}
+
+    def set_launch_config(self, config: int):
+        """Apply a launch shape in pcv_autotune's encoding."""
+        self._check(self._lib.pcv_set_launch_config(self._ctx, int(config)), "pcv_set_launch_config")
+
+    def launch_config(self) -> int:
+        cfg = ctypes.c_int32()
+        self._check(self._lib.pcv_get_launch_config(self._ctx, ctypes.byref(cfg)), "pcv_get_launch_config")
+        return cfg.value
 
     def adapt(self, n_adapt: int, target_accept: float = 0.8) -> dict:
         """Window adaptation of the step size and diagonal inverse mass over

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # (each instance emits one pair's kernels) and once more for the dispatchers,
 # so the long device compilations run in parallel.
 _VALU_INST = [("k_valu.hip", [f"-DPCV_VALU_T={t}", f"-DPCV_VALU_FAM={fam}"], f"k_valu_{t}_{fam}.o")
-              for t in ("double", "float") for fam in range(4)]
+              for t in ("double", "float") for fam in range(5)]
 SOURCES = [("api.hip", [], "api.o"), ("k_common.hip", [], "k_common.o"), ("k_valu.hip", [], "k_valu.o"),
            ("k_mfma.hip", [], "k_mfma.o"), ("posthoc.hip", [], "posthoc.o")] + _VALU_INST
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -23,13 +23,13 @@ hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb
 hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, const double* uscr, int ns, int mode,
                               hipStream_t st);
 int valu_pb(int64_t p, bool fp64);
-hipError_t launch_mfma(const DevModel& m, const uint4* Xpk, const float* ty, const int32_t* tfid, float* Gpart,
-                       double* Vpart, int n_tiles, int tiles_per_split, int n_splits, int fwd, bool value,
-                       hipStream_t st);
-hipError_t launch_mfma_pack(const double* X, int64_t n, int P, int n_tiles, uint4* out, hipStream_t st);
+hipError_t launch_mfma(const DevModel& m, int shape, const uint4* Xpk, const float* ty, const int32_t* tfid,
+                       const uint32_t* tflag, float* Gpart, double* Vpart, int n_tiles, int tiles_per_split,
+                       int n_splits, int fwd, bool value, hipStream_t st);
+hipError_t launch_mfma_pack(const double* X, int64_t n, int P, int n_tiles, int shape, uint4* out, hipStream_t st);
 int mfma_chain_tile();
 int mfma_rows_per_tile();
-int mfma_nfrag(int P);
+int mfma_nfrag(int P, int shape);
 hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st);
 hipError_t launch_reduce_f32(const DevModel& m, const float* G, int ns, int mode, hipStream_t st);
 hipError_t launch_reduce_f64(const DevModel& m, const double* G, int ns, int mode, hipStream_t st);
@@ -69,7 +69,10 @@ struct pcv_ctx_s {
   void* Xv = nullptr;
   int32_t* wave_rows = nullptr;
   // MFMA
-  uint4* Xpk = nullptr;
+  uint4* Xpk = nullptr;            // X packed for the current MFMA shape
+  uint4* Xpk_shape[2] = {nullptr, nullptr};   // packed X of each shape (made on first use)
+  int mshape = MFMA_SHAPE_32X32X16;
+  uint32_t* tflag = nullptr;       // [n_tiles][chain tiles] waves with a non-train or padded row
   float* ty = nullptr;
   int32_t* tfid = nullptr;
   float* Gpart = nullptr;
@@ -215,8 +218,8 @@ pcv_status split_partials(pcv_ctx ctx, bool value) {
   if (ctx->path == PATH_MFMA) {
     if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
     timing_begin(ctx);
-    CK(launch_mfma(m, ctx->Xpk, ctx->ty, ctx->tfid, ctx->Gpart, ctx->Vpart, ctx->n_tiles, ctx->tiles_per_split,
-                   ctx->n_splits, ctx->fwd, value, ctx->st));
+    CK(launch_mfma(m, ctx->mshape, ctx->Xpk, ctx->ty, ctx->tfid, ctx->tflag, ctx->Gpart, ctx->Vpart, ctx->n_tiles,
+                   ctx->tiles_per_split, ctx->n_splits, ctx->fwd, value, ctx->st));
     timing_end(ctx);
     return PCV_OK;
   }
@@ -244,7 +247,7 @@ pcv_status split_reduce(pcv_ctx ctx, int mode) {
   if (ctx->path == PATH_VALU_SPLIT) {
     // the split sums, prior (and hierarchical chain rule) and update per
     // (entry, chain) thread
-    if (ctx->m.family == FAM_HIER) {
+    if (hier_family(ctx->m.family)) {
       CK(launch_valu_finish(ctx->m, ctx->Gpart64, ctx->uscr, ctx->n_splits, mode, ctx->st));
     } else {
       CK(launch_reduce_f64(ctx->m, ctx->Gpart64, ctx->n_splits, mode, ctx->st));
@@ -368,7 +371,7 @@ pcv_status apply_valu_splits(pcv_ctx ctx, int ns) {
   }
   CK(hipMemcpy(ctx->wave_rows, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice));
   m.wave_rows = ctx->wave_rows;
-  const bool hier = m.family == FAM_HIER;
+  const bool hier = hier_family(m.family);
   if (hier) {
     const int32_t* go = ctx->group_of_host.data();
     std::vector<int32_t> gs(2 * static_cast<size_t>(m.n_groups));
@@ -476,13 +479,34 @@ pcv_status resolve_scratch(pcv_ctx ctx) {
 }
 }  // namespace
 
+namespace {
+// MFMA path: switch the gradient kernel's tile shape, packing X for it on
+// first use (the fp64 design stays resident for that).
+pcv_status apply_mfma_shape(pcv_ctx ctx, int shape) {
+  if (shape != MFMA_SHAPE_16X16X32 && shape != MFMA_SHAPE_32X32X16)
+    return fail(ctx, PCV_ERR_INVALID_ARG, "unknown MFMA shape");
+  if (!ctx->Xpk_shape[shape]) {
+    const int P = static_cast<int>(ctx->m.p);
+    const size_t nfr = static_cast<size_t>(ctx->n_tiles) * mfma_nfrag(P, shape) * 64;
+    uint4* xp;
+    TRY(dalloc(ctx, &xp, nfr));
+    CK(launch_mfma_pack(ctx->m.X64, ctx->m.n, P, ctx->n_tiles, shape, xp, ctx->st));
+    ctx->Xpk_shape[shape] = xp;
+  }
+  ctx->Xpk = ctx->Xpk_shape[shape];
+  ctx->mshape = shape;
+  drop_graph(ctx);
+  return PCV_OK;
+}
+}  // namespace
+
 static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, const double* y,
                             const pcv_folds* fm) {
   if (!md || !X || !y || !fm) return fail(ctx, PCV_ERR_INVALID_ARG, "null argument");
   const int64_t n = md->n, p = md->p;
   if (n <= 0 || p <= 0 || md->K <= 0) return fail(ctx, PCV_ERR_INVALID_ARG, "n, p and K must be positive");
   if (md->L < 2 || md->L > 64) return fail(ctx, PCV_ERR_INVALID_ARG, "L must be in [2, 64]");
-  if (md->family < 0 || md->family > 3) return fail(ctx, PCV_ERR_INVALID_ARG, "unknown family");
+  if (md->family < 0 || md->family > 4) return fail(ctx, PCV_ERR_INVALID_ARG, "unknown family");
   if (md->precision < 0 || md->precision > 4) return fail(ctx, PCV_ERR_INVALID_ARG, "unknown precision");
   if (md->x_format != PCV_X_FP64 && md->x_format != PCV_X_BF16_HILO)
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown x_format");
@@ -498,9 +522,12 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   if (md->batch_size < 1 || md->batches_per_block < 1 || md->n_blocks < 1 || md->n_blocks > MAX_BLOCKS)
     return fail(ctx, PCV_ERR_INVALID_ARG, "batch_size, batches_per_block >= 1 and 1 <= n_blocks <= 64 required");
   if (md->n_warmup < 0 || md->chain_offset < 0) return fail(ctx, PCV_ERR_INVALID_ARG, "negative n_warmup or chain_offset");
-  const bool hier = md->family == PCV_FAMILY_HIER_LOGISTIC;
+  const bool hier = md->family == PCV_FAMILY_HIER_LOGISTIC || md->family == PCV_FAMILY_HIER_GAUSSIAN;
+  const bool hgauss = md->family == PCV_FAMILY_HIER_GAUSSIAN;
   if (hier && (md->n_groups <= 0 || !md->group_of)) return fail(ctx, PCV_ERR_INVALID_ARG, "hierarchical family needs groups");
-  const int64_t d = hier ? p + 2 + md->n_groups : p;
+  const int64_t d = hier ? p + (hgauss ? 3 : 2) + md->n_groups : p;
+  if (hgauss && md->scores)
+    return fail(ctx, PCV_ERR_UNSUPPORTED, "HS and DSS are not built for the hierarchical Gaussian family");
   // models in one launch (Appendix B): M x K posteriors, model-major
   const int M = md->n_models > 1 ? md->n_models : 1;
   if (md->n_models < 0) return fail(ctx, PCV_ERR_INVALID_ARG, "n_models must be >= 0");
@@ -508,7 +535,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     if (!md->model_mask) return fail(ctx, PCV_ERR_INVALID_ARG, "n_models > 1 needs model_mask");
     for (int64_t i = 0; i < static_cast<int64_t>(M) * p; ++i)
       if (md->model_mask[i] > 1) return fail(ctx, PCV_ERR_INVALID_ARG, "model_mask entries must be 0 or 1");
-    if (hier) return fail(ctx, PCV_ERR_UNSUPPORTED, "several models in one launch: GLM families only");
+    if (hier && md->precision != PCV_PREC_FP64 && md->precision != PCV_PREC_FP32)
+      return fail(ctx, PCV_ERR_UNSUPPORTED, "several hierarchical models in one launch: fp64 and fp32 paths");
     if (md->scores) return fail(ctx, PCV_ERR_UNSUPPORTED, "several models in one launch: no scores");
     if (md->precision == PCV_PREC_FP64_UNFUSED)
       return fail(ctx, PCV_ERR_UNSUPPORTED, "several models in one launch: not on the plain fp64 path");
@@ -529,7 +557,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
         return fail(ctx, PCV_ERR_INVALID_ARG, "prior_scale must be > 0");
   for (int64_t i = 0; i < n; ++i) {
     const double v = y[i];
-    if ((md->family == PCV_FAMILY_LOGISTIC || hier) && !(v == 0.0 || v == 1.0))
+    if ((md->family == PCV_FAMILY_LOGISTIC || md->family == PCV_FAMILY_HIER_LOGISTIC) && !(v == 0.0 || v == 1.0))
       return fail(ctx, PCV_ERR_INVALID_ARG, "Bernoulli responses must be 0 or 1");
     if (md->family == PCV_FAMILY_POISSON && !(v >= 0.0 && v == std::floor(v)))
       return fail(ctx, PCV_ERR_INVALID_ARG, "Poisson responses must be non-negative integers");
@@ -681,7 +709,12 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   std::vector<double> prior_prec(d, 1.0);
   double prior_const = 0.0;
   const double half_log_2pi = 0.5 * std::log(2.0 * M_PI);
-  if (hier) {
+  if (hgauss) {
+    // beta, mu, z standard normal; sigma_a, sigma_y half-normal with variance
+    // HGAUSS_SCALE_VAR (their log-Jacobians and exponents are in prior_quad)
+    prior_const = -static_cast<double>(d - 2) * half_log_2pi +
+                  2.0 * (std::log(2.0) - 0.5 * std::log(2.0 * M_PI * HGAUSS_SCALE_VAR));
+  } else if (hier) {
     prior_const = -static_cast<double>(d - 1) * half_log_2pi + (std::log(2.0) - half_log_2pi);
   } else {
     for (int64_t j = 0; j < d; ++j) {
@@ -721,6 +754,12 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   m.prior_prec = pprec;
   m.rowc = rowc;
   m.fold_const = fconst;
+  {
+    std::vector<double> ntr(train_cnt.begin(), train_cnt.end());
+    double* nt;
+    TRY(upload(ctx, &nt, ntr.data(), ntr.size()));
+    m.ntrain = nt;
+  }
   int32_t *tp, *tr;
   TRY(upload(ctx, &tp, test_ptr.data(), test_ptr.size()));
   TRY(upload(ctx, &tr, test_rows.data(), test_rows.size()));
@@ -891,9 +930,32 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     ctx->n_splits = (ctx->n_tiles + ctx->tiles_per_split - 1) / ctx->tiles_per_split;
     if (ctx->tiles_per_split < 1 || static_cast<int64_t>(ctx->n_splits) * ctx->tiles_per_split < ctx->n_tiles)
       return fail(ctx, PCV_ERR_DEVICE, "internal error: row splits do not cover the rows");
-    const size_t nfr = static_cast<size_t>(ctx->n_tiles) * mfma_nfrag(static_cast<int>(p)) * 64;
-    TRY(dalloc(ctx, &ctx->Xpk, nfr));
-    CK(launch_mfma_pack(X64, n, static_cast<int>(p), ctx->n_tiles, ctx->Xpk, ctx->st));
+    TRY(apply_mfma_shape(ctx, MFMA_SHAPE_32X32X16));
+    // per (tile, chain tile): bit w set when a chain of wave w has a
+    // non-train row in the tile, or the tile holds padded rows (past n);
+    // those waves take the masked epilogue
+    {
+      const int cpw = mfma_chain_tile() / 8;   // chains per wave
+      std::vector<uint32_t> fl(static_cast<size_t>(ctx->n_tiles) * n_ct, 0u);
+      if (n % R != 0)
+        for (int c = 0; c < n_ct; ++c) fl[static_cast<size_t>(ctx->n_tiles - 1) * n_ct + c] = 0xFFu;
+      for (int kp = 0; kp < M * K; ++kp) {
+        const int k = kp % K;
+        std::vector<int> tiles;
+        if (fm->kind == PCV_FOLDS_INTERVALS) {
+          const int64_t lo = ivals[4 * k + 2], hi = ivals[4 * k + 3];
+          for (int64_t t = lo / R; hi > lo && t <= (hi - 1) / R; ++t) tiles.push_back(static_cast<int>(t));
+        } else {
+          for (int32_t q = test_ptr[k]; q < test_ptr[k + 1]; ++q) tiles.push_back(test_rows[q] / R);
+        }
+        for (int64_t c = static_cast<int64_t>(kp) * md->L; c < static_cast<int64_t>(kp + 1) * md->L; ++c) {
+          const int cti = static_cast<int>(c / mfma_chain_tile());
+          const uint32_t bit = 1u << static_cast<int>((c % mfma_chain_tile()) / cpw);
+          for (int t : tiles) fl[static_cast<size_t>(t) * n_ct + cti] |= bit;
+        }
+      }
+      TRY(upload(ctx, &ctx->tflag, fl.data(), fl.size()));
+    }
     std::vector<float> ty(static_cast<size_t>(ctx->n_tiles) * R, 0.f);
     std::vector<int32_t> tf(static_cast<size_t>(ctx->n_tiles) * R, -2);
     for (int64_t i = 0; i < n; ++i) {
@@ -1754,6 +1816,19 @@ pcv_status apply_splits(pcv_ctx ctx, int ns) {
   return PCV_OK;
 }
 
+// MFMA launch shape as one autotuner config: MFMA_CFG_SHAPE * shape + splits.
+constexpr int MFMA_CFG_SHAPE = 256;
+bool mfma_cfg_ok(pcv_ctx ctx, int cfg) {
+  const int shape = cfg / MFMA_CFG_SHAPE, ns = cfg % MFMA_CFG_SHAPE;
+  return cfg >= 0 && (shape == MFMA_SHAPE_16X16X32 || shape == MFMA_SHAPE_32X32X16) && ns >= 1 &&
+         ns <= std::min(64, ctx->n_tiles);
+}
+pcv_status apply_mfma_cfg(pcv_ctx ctx, int cfg) {
+  if (!mfma_cfg_ok(ctx, cfg)) return fail(ctx, PCV_ERR_INVALID_ARG, "invalid MFMA launch configuration");
+  TRY(apply_mfma_shape(ctx, cfg / MFMA_CFG_SHAPE));
+  return apply_splits(ctx, cfg % MFMA_CFG_SHAPE);
+}
+
 bool waves_ok(pcv_ctx ctx, int W) {
   return W >= 1 && W <= 8 && !(ctx->pb >= 32 && W > 4) && ctx->m.n / W >= 8 &&
          valu_smem_bytes(ctx->fp64, W, ctx->m.family, ctx->m.n_groups, ctx->pb) <= 65536;
@@ -1811,11 +1886,11 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   std::vector<TuneEntry> cache = cache_path ? cache_read(cache_path) : std::vector<TuneEntry>{};
   for (const TuneEntry& e : cache) {
     if (e.key != key) continue;
-    const bool valid = ctx->path == PATH_MFMA        ? (e.cfg >= 1 && e.cfg <= ctx->n_tiles)
+    const bool valid = ctx->path == PATH_MFMA        ? mfma_cfg_ok(ctx, e.cfg)
                        : ctx->path == PATH_VALU_SPLIT ? (e.cfg >= 1 && e.cfg <= valu_split_max(ctx))
                                                       : waves_ok(ctx, e.cfg);
     if (!valid) break;   // stale entry: tune again
-    if (ctx->path == PATH_MFMA) TRY(apply_splits(ctx, e.cfg));
+    if (ctx->path == PATH_MFMA) TRY(apply_mfma_cfg(ctx, e.cfg));
     else if (ctx->path == PATH_VALU_SPLIT) TRY(apply_valu_splits(ctx, e.cfg));
     else TRY(apply_waves(ctx, e.cfg));
     if (config) *config = e.cfg;
@@ -1829,13 +1904,17 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
       if (ns >= 1 && ns <= valu_split_max(ctx) && std::find(cand.begin(), cand.end(), ns) == cand.end())
         cand.push_back(ns);
   } else if (ctx->path == PATH_MFMA) {
+    // both MFMA tile shapes, each with row-split counts around the analytic
+    // choice: config = MFMA_CFG_SHAPE * shape + splits
     const int ns0 = ctx->n_splits, hi = std::min(64, ctx->n_tiles);
-    for (int ns : {ns0 / 2, ns0 - 2, ns0 - 1, ns0, ns0 + 1, ns0 + 2, 2 * ns0}) {
-      if (ns < 1 || ns > hi) continue;
-      const int tps = (ctx->n_tiles + ns - 1) / ns;
-      const int nsp = (ctx->n_tiles + tps - 1) / tps;
-      if (std::find(cand.begin(), cand.end(), nsp) == cand.end()) cand.push_back(nsp);
-    }
+    for (int shape : {MFMA_SHAPE_32X32X16, MFMA_SHAPE_16X16X32})
+      for (int ns : {ns0 / 2, ns0 - 2, ns0 - 1, ns0, ns0 + 1, ns0 + 2, 2 * ns0}) {
+        if (ns < 1 || ns > hi) continue;
+        const int tps = (ctx->n_tiles + ns - 1) / ns;
+        const int nsp = (ctx->n_tiles + tps - 1) / tps;
+        const int cfg = MFMA_CFG_SHAPE * shape + nsp;
+        if (std::find(cand.begin(), cand.end(), cfg) == cand.end()) cand.push_back(cfg);
+      }
   } else {
     for (int W : {1, 2, 4, 8})
       if (waves_ok(ctx, W)) cand.push_back(W);
@@ -1852,8 +1931,8 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   for (int pass = 0; pass < 2 && s == PCV_OK; ++pass) {
     for (size_t ci = 0; ci < cand.size(); ++ci) {
       const int c = cand[ci];
-      s = ctx->path == PATH_MFMA ? apply_splits(ctx, c) : ctx->path == PATH_VALU ? apply_waves(ctx, c)
-                                                                                 : apply_valu_splits(ctx, c);
+      s = ctx->path == PATH_MFMA ? apply_mfma_cfg(ctx, c) : ctx->path == PATH_VALU ? apply_waves(ctx, c)
+                                                                                   : apply_valu_splits(ctx, c);
       double t = 0.0;
       if (s == PCV_OK) s = time_hot(ctx, reps, &t);
       if (s != PCV_OK) break;
@@ -1869,7 +1948,7 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
     }
   ctx->timing = timing;
   if (s != PCV_OK) return s;
-  TRY(ctx->path == PATH_MFMA   ? apply_splits(ctx, best)
+  TRY(ctx->path == PATH_MFMA   ? apply_mfma_cfg(ctx, best)
       : ctx->path == PATH_VALU ? apply_waves(ctx, best)
                                : apply_valu_splits(ctx, best));
   if (config) *config = best;
@@ -1886,6 +1965,28 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
     if (!cache_write(cache_path, cache))
       return fail(ctx, PCV_ERR_INVALID_ARG, std::string("cannot write the tuning cache ") + cache_path);
   }
+  return PCV_OK;
+}
+
+pcv_status pcv_set_launch_config(pcv_ctx ctx, int32_t config) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (ctx->path == PATH_UNFUSED) return fail(ctx, PCV_ERR_UNSUPPORTED, "the plain fp64 path has no launch shape");
+  const bool valid = ctx->path == PATH_MFMA        ? mfma_cfg_ok(ctx, config)
+                     : ctx->path == PATH_VALU_SPLIT ? (config >= 1 && config <= valu_split_max(ctx))
+                                                    : waves_ok(ctx, config);
+  if (!valid) return fail(ctx, PCV_ERR_INVALID_ARG, "launch configuration out of range for this context");
+  if (ctx->path == PATH_MFMA) TRY(apply_mfma_cfg(ctx, config));
+  else if (ctx->path == PATH_VALU_SPLIT) TRY(apply_valu_splits(ctx, config));
+  else TRY(apply_waves(ctx, config));
+  return PCV_OK;
+}
+
+pcv_status pcv_get_launch_config(pcv_ctx ctx, int32_t* config) {
+  if (!usable(ctx)) return PCV_ERR_STATE;
+  if (!config) return fail(ctx, PCV_ERR_INVALID_ARG, "null output");
+  if (ctx->path == PATH_UNFUSED) return fail(ctx, PCV_ERR_UNSUPPORTED, "the plain fp64 path has no launch shape");
+  *config = ctx->path == PATH_MFMA ? MFMA_CFG_SHAPE * ctx->mshape + ctx->n_splits
+            : ctx->path == PATH_VALU_SPLIT ? ctx->n_splits : ctx->W;
   return PCV_OK;
 }
 
@@ -2035,7 +2136,10 @@ pcv_status pcv_timing_read(pcv_ctx ctx, double* ms_sum, int64_t* n_launches, con
   timing_collect(ctx);
   if (ms_sum) *ms_sum = ctx->ms_acc;
   if (n_launches) *n_launches = ctx->n_launch;
-  if (kernel_name) *kernel_name = kGradKernelName[ctx->path];
+  if (kernel_name)
+    *kernel_name = ctx->path == PATH_MFMA && ctx->mshape == MFMA_SHAPE_32X32X16
+                       ? "k_mfma32 (bf16 split 32x32x16 MFMA value+gradient)"
+                       : kGradKernelName[ctx->path];
   if (reset) {
     ctx->ms_acc = 0.0;
     ctx->n_launch = 0;

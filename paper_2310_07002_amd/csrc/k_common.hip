@@ -118,6 +118,8 @@ __global__ __launch_bounds__(64 * accept_max_y<FAM>()) void k_accept(DevModel m,
     k1 += 0.5 * m.minv[j] * p * p;
   }
   const int k = fold_of_chain(m, cc);
+  // the hierarchical Gaussian's -n_train log sigma_y (prior_quad's extra term)
+  if (FAM == FAM_HGAUSS && y == 0) pq -= m.ntrain[k] * m.q1[(m.p + 2) * m.C + cc];
   const int beg = m.test_ptr[k], nt = m.test_ptr[k + 1] - beg;
   lp = log_pred_rows<FAM>(m, m.q1, cc, beg + static_cast<int>(static_cast<int64_t>(nt) * y / Y),
                           beg + static_cast<int>(static_cast<int64_t>(nt) * (y + 1) / Y));
@@ -200,6 +202,7 @@ __global__ void k_rowconst(DevModel m, double* rowc) {
   if (i >= m.n) return;
   double v = 0.0;
   if (m.family == FAM_GAUSS) v = -0.5 * log(2.0 * M_PI / m.inv_sigma2);
+  else if (m.family == FAM_HGAUSS) v = -0.5 * log(2.0 * M_PI);   // -log sigma_y is per chain
   else if (m.family == FAM_POIS) v = -lgamma(m.y64[i] + 1.0);
   rowc[i] = v;
 }
@@ -468,6 +471,7 @@ __global__ void k_kick_drift(DevModel m) {
       case FAM_LOGIT: hipLaunchKernelGGL((KERNEL<FAM_LOGIT>), grid, block, 0, st, __VA_ARGS__); break; \
       case FAM_POIS: hipLaunchKernelGGL((KERNEL<FAM_POIS>), grid, block, 0, st, __VA_ARGS__); break;   \
       case FAM_HIER: hipLaunchKernelGGL((KERNEL<FAM_HIER>), grid, block, 0, st, __VA_ARGS__); break;   \
+      case FAM_HGAUSS: hipLaunchKernelGGL((KERNEL<FAM_HGAUSS>), grid, block, 0, st, __VA_ARGS__); break; \
     }                                                                                            \
   } while (0)
 

@@ -42,6 +42,7 @@ struct MfmaArgs {
   const int32_t* tfid; // [n_tiles*32] fold index per row (INDEX encoding)
   float* Gpart;        // [n_splits][P][C]
   double* Vpart;       // [n_splits][C]
+  const uint32_t* tflag;  // [n_tiles][chain tiles]: bit w = wave w sees a non-train or padded row
   int n_tiles, tiles_per_split, n_splits;
 };
 
@@ -432,6 +433,383 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// 32x32x16 variant.  The same product as k_mfma on v_mfma_f32_32x32x16_bf16:
+// a wave owns 32 chains (one 32-wide N block) and a 32-row tile is one M
+// block, so each MFMA does twice the work of a 16x16x32 one and the matrix
+// cores need half the issue slots, which the epilogue's VALU work can use.
+// The D layout of a 32x32 accumulator (lane l, element i: row
+// 8(i/4) + 4(l/32) + i%4, column l%32) gives each lane 16 rows of ONE chain.
+// The adjoint's K index (rows) follows that layout: K half kh, lane half h,
+// element e is row 16 kh + (e < 4 ? 4h + e : 8 + 4h + e - 4), so the
+// residuals of accumulator elements 8kh..8kh+7 are the adjoint's B operand
+// for K half kh as they stand.
+//
+// Masks leave the per-element path: a per-(tile, chain tile) word, built on
+// the host from the fold encoding, has bit w set when some chain of wave w
+// has a non-train row in the tile (or the tile has padded rows).  Waves whose
+// bit is clear (all but a few tiles: a fold's non-train rows are a small
+// fraction of n) take an epilogue without any mask arithmetic.
+// ---------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// fragments per 32-row tile: forward P/16 K blocks x 2 planes; adjoint
+// P/32 M blocks x 2 K halves x 2 planes
+__host__ __device__ constexpr int m2_nfrag_fwd(int P) { return (P / 16) * 2; }
+__host__ __device__ constexpr int m2_nfrag(int P) { return m2_nfrag_fwd(P) + (P / 32) * 4; }
+
+// Row (within the tile) of accumulator element i for lane half h.
+__host__ __device__ constexpr int m2_row(int i, int h) { return 8 * (i >> 2) + 4 * h + (i & 3); }
+
+// The pair (r0, r1) as packed bf16 hi and lo words: hi = bf16(r) (round to
+// nearest even, v_cvt_pk_bf16_f32), lo = bf16(r - hi).
+__device__ __forceinline__ void m2_split2(float r0, float r1, uint32_t& hi, uint32_t& lo) {
+  const bf16x2 h = __builtin_convertvector(f32x2{r0, r1}, bf16x2);
+  const uint32_t hw = __builtin_bit_cast(uint32_t, h);
+  const float h0 = __builtin_bit_cast(float, hw << 16);
+  const float h1 = __builtin_bit_cast(float, hw & 0xffff0000u);
+  const bf16x2 l = __builtin_convertvector(f32x2{r0 - h0, r1 - h1}, bf16x2);
+  hi = hw;
+  lo = __builtin_bit_cast(uint32_t, l);
+}
+
+template <int FAM, int P, int FWD, bool VALUE, int FK>
+__global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
+  constexpr int KB = P / 16;                 // forward K blocks
+  constexpr int MB = P / 32;                 // adjoint M blocks
+  constexpr int NFF = m2_nfrag_fwd(P);
+  constexpr int NF = m2_nfrag(P);
+  constexpr int NST = NF * 64 / (64 * MF_WAVES);  // uint4 staged per thread
+  constexpr int NT = FWD == 5 ? 3 : 2;
+  constexpr int NBUF = 4;
+  constexpr int NG = KB + 2 * MB;            // MFMA groups per tile: forward K blocks, adjoint (M block, K half)
+  static_assert(NST * 64 * MF_WAVES == NF * 64, "staging must tile the fragments");
+  static_assert(NST == 2 || NST == 4, "two or four staged vectors per thread");
+  static_assert(NG == 8 || NG == 16, "8 or 16 groups per tile");
+
+  __shared__ __align__(16) uint4 sfrag[NBUF][NF * 64];
+  __shared__ __align__(16) float sy[NBUF][MF_ROWS];
+  __shared__ __align__(16) int32_t sf[NBUF][MF_ROWS];
+  __shared__ uint32_t sflag[NBUF];
+
+  const DevModel& m = a.m;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int hh = lane >> 5;
+  const int l32 = lane & 31;
+  const int task = mf_xcd_task(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
+  const int n_ct = static_cast<int>((m.C + MF_CHAIN_TILE - 1) / MF_CHAIN_TILE);
+  const int sp = task / n_ct;
+  const int ct = task - sp * n_ct;
+  const int64_t cbase = static_cast<int64_t>(ct) * MF_CHAIN_TILE + wave * MF_CHAINS_PER_WAVE;
+  const bool wave_active = cbase < m.C;
+  const int t_beg = sp * a.tiles_per_split;
+  const int t_end = min(a.n_tiles, t_beg + a.tiles_per_split);
+  const int t_last = t_end > t_beg ? t_end - 1 : t_beg;
+
+  // this lane's chain (lanes l and l + 32 share it)
+  const int64_t cidx = cbase + l32;
+  const bool cvalid = cidx < m.C;
+  const int kf = fold_of_chain(m, cvalid ? cidx : m.C - 1);
+  int elo = 0, ehi = 0;
+  if (FK == PCV_FOLDS_INTERVALS) {
+    elo = m.ivals[4 * kf + 2];
+    ehi = m.ivals[4 * kf + 3];
+  }
+
+  // theta as the B operand: lane holds theta[16 kb + 8 hh + e][chain]
+  bf16x8 th[NT][KB];
+  {
+    const uint8_t* mrow = cvalid ? mask_row(m, cidx) : nullptr;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const uint64_t mbits = mrow ? *reinterpret_cast<const uint64_t*>(mrow + kb * 16 + 8 * hh) : ~0ull;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = kb * 16 + 8 * hh + e;
+        const double t = cvalid && ((mbits >> (8 * e)) & 0xffu)
+                             ? m.q1[static_cast<int64_t>(j) * m.C + cidx] * mf_theta_scale<FAM>() : 0.0;
+        if (NT == 2) {
+          const float t32 = static_cast<float>(t);
+          const __bf16 h = to_bf16(t32);
+          th[0][kb][e] = h;
+          th[1][kb][e] = to_bf16(t32 - static_cast<float>(h));
+        } else {
+          const __bf16 h = to_bf16(static_cast<float>(t));
+          const double r1 = t - static_cast<double>(static_cast<float>(h));
+          const __bf16 mdl = to_bf16(static_cast<float>(r1));
+          const double r2 = r1 - static_cast<double>(static_cast<float>(mdl));
+          th[0][kb][e] = h;
+          th[1][kb][e] = mdl;
+          th[NT - 1][kb][e] = to_bf16(static_cast<float>(r2));
+        }
+      }
+    }
+  }
+
+  f32x16 gacc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) gacc[mb][i] = 0.f;
+  double vacc = 0.0;
+  const float is2 = static_cast<float>(m.inv_sigma2);
+  const int nrows = static_cast<int>(m.n);
+
+  // ---- staging: global -> registers -> LDS ring ---------------------------
+  uint4 st0, st1, st2, st3;
+  float my_y = 0.f;
+  int32_t my_f = 0;
+  uint32_t my_flag = 0;
+  auto load_stage = [&](int tt) {
+    const uint4* src = a.Xpk + static_cast<int64_t>(tt) * NF * 64;
+    st0 = src[tid];
+    st1 = src[512 + tid];
+    if constexpr (NST == 4) {
+      st2 = src[1024 + tid];
+      st3 = src[1536 + tid];
+    }
+    my_y = a.ty[static_cast<int64_t>(tt) * MF_ROWS + (tid & (MF_ROWS - 1))];
+    my_f = a.tfid[static_cast<int64_t>(tt) * MF_ROWS + (tid & (MF_ROWS - 1))];
+    my_flag = a.tflag[static_cast<int64_t>(tt) * n_ct + ct];
+  };
+  auto store_stage = [&](int b) {
+    sfrag[b][tid] = st0;
+    sfrag[b][512 + tid] = st1;
+    if constexpr (NST == 4) {
+      sfrag[b][1024 + tid] = st2;
+      sfrag[b][1536 + tid] = st3;
+    }
+    sy[b][tid & (MF_ROWS - 1)] = my_y;
+    sf[b][tid & (MF_ROWS - 1)] = my_f;
+    if (tid == 0) sflag[b] = my_flag;
+  };
+  auto frag = [&](int b, int f) { return __builtin_bit_cast(bf16x8, sfrag[b][f * 64 + lane]); };
+  // group g: even g -> forward K block g/2 (next tile), odd g -> adjoint (M
+  // block, K half) number g/2 (previous tile); both read two fragments
+  auto group_frag_index = [&](int g) {
+    return (g & 1) ? NFF + (g >> 1) * 2 : (g >> 1) * 2;
+  };
+
+  // prologue, as in k_mfma: slot 3 stands in for tile t_beg - 1 (zero residuals)
+  load_stage(t_beg < t_last ? t_beg : t_last);
+  store_stage(0);
+  store_stage(3);
+  load_stage(min(t_beg + 1, t_last));
+  store_stage(1);
+  load_stage(min(t_beg + 2, t_last));
+  __syncthreads();
+  f32x16 eta_cur, eta_nxt;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) eta_cur[i] = 0.f;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    const bf16x8 x0 = frag(0, 2 * kb), x1 = frag(0, 2 * kb + 1);
+    eta_cur = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, th[0][kb], eta_cur, 0, 0, 0);
+    eta_cur = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, th[1][kb], eta_cur, 0, 0, 0);
+    eta_cur = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, th[0][kb], eta_cur, 0, 0, 0);
+    if (NT == 3) {
+      eta_cur = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, th[NT - 1][kb], eta_cur, 0, 0, 0);
+      eta_cur = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, th[1][kb], eta_cur, 0, 0, 0);
+    }
+  }
+  // residual operands (as packed bf16 words): previous / current tile, K halves
+  u32x4 rph[2], rpl[2], rch[2], rcl[2];
+#pragma unroll
+  for (int kh = 0; kh < 2; ++kh) {
+    rph[kh] = u32x4{0u, 0u, 0u, 0u};
+    rpl[kh] = u32x4{0u, 0u, 0u, 0u};
+    rch[kh] = rph[kh];
+    rcl[kh] = rpl[kh];
+  }
+
+  for (int tt = t_beg; tt < t_end; ++tt) {
+    const int i = tt - t_beg;
+    const int bc = i & 3, b1 = (i + 1) & 3, b2 = (i + 2) & 3, bp = (i + 3) & 3;
+    __syncthreads();
+    store_stage(b2);
+    load_stage(min(tt + 3, t_last));
+    const uint32_t flag = __builtin_amdgcn_readfirstlane(sflag[bc]);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) eta_nxt[q] = 0.f;
+    float vt = 0.f;
+
+    // the epilogue of tile tt, one pair of elements per slot, spread over
+    // the tile's MFMA groups; waves whose flag bit is set apply the fold and
+    // row masks (a wave-uniform branch around the mask arithmetic only)
+    const bool masked = (flag >> wave) & 1u;
+    // y of this lane's 16 rows of the tile: rows 8q + 4hh + (0..3)
+    f32x4 yq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) yq[q] = *reinterpret_cast<const f32x4*>(&sy[bc][8 * q + 4 * hh]);
+    bf16x8 xa0 = frag(b1, group_frag_index(0)), xa1 = frag(b1, group_frag_index(0) + 1);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      bf16x8 xb0 = xa0, xb1 = xa1;
+      if (g + 1 < NG) {
+        const int bn = ((g + 1) & 1) ? bp : b1;
+        xb0 = frag(bn, group_frag_index(g + 1));
+        xb1 = frag(bn, group_frag_index(g + 1) + 1);
+      }
+      if ((g & 1) == 0) {
+        const int kb = g >> 1;
+        f32x16 acc = eta_nxt;
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa0, th[0][kb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa0, th[1][kb], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa1, th[0][kb], acc, 0, 0, 0);
+        if (NT == 3) {
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa0, th[NT - 1][kb], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa1, th[1][kb], acc, 0, 0, 0);
+        }
+        eta_nxt = acc;
+      } else {
+        const int mb = (g >> 1) >> 1, kh = (g >> 1) & 1;
+        const bf16x8 rh = __builtin_bit_cast(bf16x8, rph[kh]);
+        const bf16x8 rl = __builtin_bit_cast(bf16x8, rpl[kh]);
+        f32x16 acc = gacc[mb];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa0, rh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa0, rl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa1, rh, acc, 0, 0, 0);
+        gacc[mb] = acc;
+      }
+      // epilogue pairs [g*8/NG, (g+1)*8/NG) of tile tt: elements 2u, 2u+1.
+      // Gradient launches compute every residual unmasked here and clear
+      // the non-train ones after the loop; value launches mask in place.
+#pragma unroll
+      for (int u = (g * 8) / NG; u < ((g + 1) * 8) / NG; ++u) {
+        const int e0 = 2 * u;
+        const int rl0 = m2_row(e0, hh);          // rows rl0, rl0 + 1 of the tile
+        float r[2], l0[2] = {0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const float yv = yq[e0 >> 2][(e0 & 3) + q];
+          if (VALUE) mf_resid_ell0<FAM>(yv, eta_cur[e0 + q], is2, r[q], l0[q]);
+          else r[q] = mf_resid<FAM>(yv, eta_cur[e0 + q], is2);
+          if (VALUE) {
+            const int row = tt * MF_ROWS + rl0 + q;
+            bool train = row < nrows;
+            if (FK == PCV_FOLDS_INDEX) train = train & (sf[bc][rl0 + q] != kf);
+            else train = train & ((row < elo) | (row >= ehi));
+            r[q] = train ? r[q] : 0.f;
+            vt += train ? l0[q] : 0.f;
+          }
+        }
+        uint32_t hw, lw;
+        m2_split2(r[0], r[1], hw, lw);
+        const int kh = e0 >> 3, w = (e0 & 7) >> 1;
+        rch[kh][w] = hw;
+        rcl[kh][w] = lw;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      xa0 = xb0;
+      xa1 = xb1;
+    }
+    if (!VALUE && masked) {
+      // this wave's chains have non-train (or padded) rows in the tile:
+      // clear their residuals (both bf16 terms) before the adjoint uses them
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int rl = m2_row(e, hh);
+        const int row = tt * MF_ROWS + rl;
+        bool train = row < nrows;
+        if (FK == PCV_FOLDS_INDEX) train = train & (sf[bc][rl] != kf);
+        else train = train & ((row < elo) | (row >= ehi));
+        const uint32_t keep = train ? 0xFFFFFFFFu : ((e & 1) ? 0x0000FFFFu : 0xFFFF0000u);
+        const int kh = e >> 3, w = (e & 7) >> 1;
+        rch[kh][w] &= keep;
+        rcl[kh][w] &= keep;
+      }
+    }
+
+    if (VALUE) vacc += static_cast<double>(vt);
+#pragma unroll
+    for (int kh = 0; kh < 2; ++kh) {
+      rph[kh] = rch[kh];
+      rpl[kh] = rcl[kh];
+    }
+    eta_cur = eta_nxt;
+  }
+  // adjoint of the last tile
+  {
+    const int bl = (t_end - 1 - t_beg) & 3;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+#pragma unroll
+      for (int kh = 0; kh < 2; ++kh) {
+        const int f = NFF + (mb * 2 + kh) * 2;
+        const bf16x8 x0 = frag(bl, f), x1 = frag(bl, f + 1);
+        const bf16x8 rh = __builtin_bit_cast(bf16x8, rph[kh]);
+        const bf16x8 rl = __builtin_bit_cast(bf16x8, rpl[kh]);
+        f32x16 acc = gacc[mb];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, rh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, rl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, rh, acc, 0, 0, 0);
+        gacc[mb] = acc;
+      }
+    }
+  }
+
+  if (!wave_active) return;
+  if (cvalid) {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int j = mb * 32 + m2_row(q, hh);
+        a.Gpart[(static_cast<int64_t>(sp) * P + j) * m.C + cidx] = gacc[mb][q];
+      }
+  }
+  if (VALUE) {
+    double v = vacc;
+    v += __shfl_xor(v, 32);
+    if (lane < 32 && cvalid) a.Vpart[static_cast<int64_t>(sp) * m.C + cidx] = v;
+  }
+}
+
+// Pack X (fp64, row-major) for k_mfma32, split hi/lo: forward fragment
+// (kb, plane) lane l holds row l%32, columns 16 kb + 8 (l/32) + e; adjoint
+// fragment (mb, kh, plane) lane l holds column 32 mb + l%32 at the rows of
+// K half kh in accumulator order (m2_row).
+__global__ void k_mfma32_pack(const double* __restrict__ X, int64_t n, int P, int n_tiles, uint4* __restrict__ out) {
+  const int nf = m2_nfrag(P), nff = m2_nfrag_fwd(P);
+  const int64_t total = static_cast<int64_t>(n_tiles) * nf * 64;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int lane = static_cast<int>(idx % 64);
+    const int f = static_cast<int>((idx / 64) % nf);
+    const int64_t tt = idx / (64 * nf);
+    const int h = lane >> 5, l32 = lane & 31;
+    const int64_t row0 = tt * MF_ROWS;
+    const int plane = f & 1;
+    bf16x8 v;
+    if (f < nff) {
+      const int kb = f >> 1;
+      const int64_t row = row0 + l32;
+      for (int e = 0; e < 8; ++e) {
+        const int col = kb * 16 + 8 * h + e;
+        const float x = row < n ? static_cast<float>(X[row * P + col]) : 0.f;
+        const __bf16 hb = to_bf16(x);
+        v[e] = plane == 0 ? hb : to_bf16(x - static_cast<float>(hb));
+      }
+    } else {
+      const int blk = (f - nff) >> 1;        // mb * 2 + kh
+      const int mb = blk >> 1, kh = blk & 1;
+      const int col = mb * 32 + l32;
+      for (int e = 0; e < 8; ++e) {
+        const int64_t row = row0 + 16 * kh + m2_row(e, h);
+        const float x = row < n ? static_cast<float>(X[row * P + col]) : 0.f;
+        const __bf16 hb = to_bf16(x);
+        v[e] = plane == 0 ? hb : to_bf16(x - static_cast<float>(hb));
+      }
+    }
+    out[idx] = __builtin_bit_cast(uint4, v);
+  }
+}
+
 // Pack X (fp64, row-major) into the two fragment orders, split hi/lo.
 __global__ void k_mfma_pack(const double* __restrict__ X, int64_t n, int P, int n_tiles, uint4* __restrict__ out) {
   const int nf = mf_nfrag(P), nff = mf_nfrag_fwd(P), KB = P / 32;
@@ -471,36 +849,53 @@ __global__ void k_mfma_pack(const double* __restrict__ X, int64_t n, int P, int 
   }
 }
 
-template <int FAM, int P, int FWD>
+template <int FAM, int P, int FWD, int SHAPE>
 static hipError_t launch_mfma_p(const MfmaArgs& a, bool value, int nblk, hipStream_t st) {
   const bool iv = a.m.fold_kind == PCV_FOLDS_INTERVALS;
-  if (value) {
-    if (iv) hipLaunchKernelGGL((k_mfma<FAM, P, FWD, true, PCV_FOLDS_INTERVALS>), dim3(nblk), dim3(512), 0, st, a);
-    else hipLaunchKernelGGL((k_mfma<FAM, P, FWD, true, PCV_FOLDS_INDEX>), dim3(nblk), dim3(512), 0, st, a);
-  } else {
-    if (iv) hipLaunchKernelGGL((k_mfma<FAM, P, FWD, false, PCV_FOLDS_INTERVALS>), dim3(nblk), dim3(512), 0, st, a);
-    else hipLaunchKernelGGL((k_mfma<FAM, P, FWD, false, PCV_FOLDS_INDEX>), dim3(nblk), dim3(512), 0, st, a);
-  }
+#define PCV_MFMA_LAUNCH(KERN)                                                                              \
+  do {                                                                                                   \
+    if (value) {                                                                                         \
+      if (iv) hipLaunchKernelGGL((KERN<FAM, P, FWD, true, PCV_FOLDS_INTERVALS>), dim3(nblk), dim3(512), 0, st, a); \
+      else hipLaunchKernelGGL((KERN<FAM, P, FWD, true, PCV_FOLDS_INDEX>), dim3(nblk), dim3(512), 0, st, a);       \
+    } else {                                                                                             \
+      if (iv) hipLaunchKernelGGL((KERN<FAM, P, FWD, false, PCV_FOLDS_INTERVALS>), dim3(nblk), dim3(512), 0, st, a); \
+      else hipLaunchKernelGGL((KERN<FAM, P, FWD, false, PCV_FOLDS_INDEX>), dim3(nblk), dim3(512), 0, st, a);       \
+    }                                                                                                    \
+  } while (0)
+  if (SHAPE == MFMA_SHAPE_32X32X16) PCV_MFMA_LAUNCH(k_mfma32);
+  else PCV_MFMA_LAUNCH(k_mfma);
+#undef PCV_MFMA_LAUNCH
   return hipGetLastError();
 }
 
-template <int FAM>
+template <int FAM, int SHAPE>
 static hipError_t launch_mfma_f(const MfmaArgs& a, int P, int fwd, bool value, int nblk, hipStream_t st) {
-  if (P == 64 && fwd == 3) return launch_mfma_p<FAM, 64, 3>(a, value, nblk, st);
-  if (P == 64 && fwd == 5) return launch_mfma_p<FAM, 64, 5>(a, value, nblk, st);
-  if (P == 128 && fwd == 3) return launch_mfma_p<FAM, 128, 3>(a, value, nblk, st);
-  if (P == 128 && fwd == 5) return launch_mfma_p<FAM, 128, 5>(a, value, nblk, st);
+  if (P == 64 && fwd == 3) return launch_mfma_p<FAM, 64, 3, SHAPE>(a, value, nblk, st);
+  if (P == 64 && fwd == 5) return launch_mfma_p<FAM, 64, 5, SHAPE>(a, value, nblk, st);
+  if (P == 128 && fwd == 3) return launch_mfma_p<FAM, 128, 3, SHAPE>(a, value, nblk, st);
+  if (P == 128 && fwd == 5) return launch_mfma_p<FAM, 128, 5, SHAPE>(a, value, nblk, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma(const DevModel& m, const uint4* Xpk, const float* ty, const int32_t* tfid, float* Gpart,
-                       double* Vpart, int n_tiles, int tiles_per_split, int n_splits, int fwd, bool value,
-                       hipStream_t st) {
+template <int SHAPE>
+static hipError_t launch_mfma_s(const MfmaArgs& a, int P, int fwd, bool value, int nblk, hipStream_t st) {
+  switch (a.m.family) {
+    case FAM_GAUSS: return launch_mfma_f<FAM_GAUSS, SHAPE>(a, P, fwd, value, nblk, st);
+    case FAM_LOGIT: return launch_mfma_f<FAM_LOGIT, SHAPE>(a, P, fwd, value, nblk, st);
+    case FAM_POIS: return launch_mfma_f<FAM_POIS, SHAPE>(a, P, fwd, value, nblk, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mfma(const DevModel& m, int shape, const uint4* Xpk, const float* ty, const int32_t* tfid,
+                       const uint32_t* tflag, float* Gpart, double* Vpart, int n_tiles, int tiles_per_split,
+                       int n_splits, int fwd, bool value, hipStream_t st) {
   MfmaArgs a;
   a.m = m;
   a.Xpk = Xpk;
   a.ty = ty;
   a.tfid = tfid;
+  a.tflag = tflag;
   a.Gpart = Gpart;
   a.Vpart = Vpart;
   a.n_tiles = n_tiles;
@@ -509,21 +904,19 @@ hipError_t launch_mfma(const DevModel& m, const uint4* Xpk, const float* ty, con
   const int n_ct = static_cast<int>((m.C + MF_CHAIN_TILE - 1) / MF_CHAIN_TILE);
   const int nblk = n_ct * n_splits;
   const int P = static_cast<int>(m.p);
-  switch (m.family) {
-    case FAM_GAUSS: return launch_mfma_f<FAM_GAUSS>(a, P, fwd, value, nblk, st);
-    case FAM_LOGIT: return launch_mfma_f<FAM_LOGIT>(a, P, fwd, value, nblk, st);
-    case FAM_POIS: return launch_mfma_f<FAM_POIS>(a, P, fwd, value, nblk, st);
-  }
+  if (shape == MFMA_SHAPE_32X32X16) return launch_mfma_s<MFMA_SHAPE_32X32X16>(a, P, fwd, value, nblk, st);
+  if (shape == MFMA_SHAPE_16X16X32) return launch_mfma_s<MFMA_SHAPE_16X16X32>(a, P, fwd, value, nblk, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_pack(const double* X, int64_t n, int P, int n_tiles, uint4* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_mfma_pack, dim3(1024), dim3(256), 0, st, X, n, P, n_tiles, out);
+hipError_t launch_mfma_pack(const double* X, int64_t n, int P, int n_tiles, int shape, uint4* out, hipStream_t st) {
+  if (shape == MFMA_SHAPE_32X32X16) hipLaunchKernelGGL(k_mfma32_pack, dim3(1024), dim3(256), 0, st, X, n, P, n_tiles, out);
+  else hipLaunchKernelGGL(k_mfma_pack, dim3(1024), dim3(256), 0, st, X, n, P, n_tiles, out);
   return hipGetLastError();
 }
 
 int mfma_chain_tile() { return MF_CHAIN_TILE; }
 int mfma_rows_per_tile() { return MF_ROWS; }
-int mfma_nfrag(int P) { return mf_nfrag(P); }
+int mfma_nfrag(int P, int shape) { return shape == MFMA_SHAPE_32X32X16 ? m2_nfrag(P) : mf_nfrag(P); }
 
 }  // namespace pcv

@@ -75,19 +75,21 @@ __device__ __forceinline__ void block_groups(const DevModel& m, const int32_t* w
   }
 }
 
+// FAM_HGAUSS also returns (wave 0) qsum = sum over training rows of
+// (y - eta)^2 / sigma_y^2, from which the log sigma_y gradient follows.
 template <typename T, int FAM, int PB, bool VALUE>
 __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict__ Xv, int lane, int wave,
                                           int W, int64_t cc, int k, int elo, int ehi, T (&G)[PB],
-                                          double& val, char* smem, bool want_value = true,
+                                          double& val, double& qsum, char* smem, bool want_value = true,
                                           const int32_t* wave_rows = nullptr) {
   constexpr int JC = valu_jc<T, PB>();
   T* red = reinterpret_cast<T*>(smem);                                      // [W][JC][64]
   double* vred = reinterpret_cast<double*>(smem + sizeof(T) * W * JC * 64);  // [W][64]
   T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);  // [G][64]
-  T* rg = zt + (FAM == FAM_HIER ? m.n_groups * 64 : 0);                      // [G][64]
-  T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);                    // [PB][64]
+  T* rg = zt + (hier_fam<FAM>() ? m.n_groups * 64 : 0);                      // [G][64]
+  T* gfin = rg + (hier_fam<FAM>() ? m.n_groups * 64 : 0);                    // [PB][64]
   T* ef = gfin + PB * 64;                                                     // [W][2][64]
-  int* eg = reinterpret_cast<int*>(ef + (FAM == FAM_HIER ? W * 2 * 64 : 0));  // [W][2]
+  int* eg = reinterpret_cast<int*>(ef + (hier_fam<FAM>() ? W * 2 * 64 : 0));  // [W][2]
 
   const int32_t* wr = wave_rows ? wave_rows : m.wave_rows;
   T th[PB];
@@ -96,21 +98,26 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
   for (int j = 0; j < PB; ++j)
     th[j] = (j < m.p && covariate_used(mrow, j)) ? static_cast<T>(m.q1[j * m.C + cc]) : T(0);
   T mu = 0;
-  if (FAM == FAM_HIER) {
+  if (hier_fam<FAM>()) {
     // tau z_g only for the groups of this workgroup's rows; rg cleared for all
     mu = static_cast<T>(m.q1[m.p * m.C + cc]);
     const T tau = static_cast<T>(exp(m.q1[(m.p + 1) * m.C + cc]));
+    const int64_t z0 = hier_z0(m);
     int glo, ghi;
     block_groups(m, wr, W, glo, ghi);
     for (int g = glo + wave; g <= ghi; g += W)
-      zt[g * 64 + lane] = tau * static_cast<T>(m.q1[(m.p + 2 + g) * m.C + cc]);
+      zt[g * 64 + lane] = tau * static_cast<T>(m.q1[(z0 + g) * m.C + cc]);
     for (int g = wave; g < m.n_groups; g += W) rg[g * 64 + lane] = T(0);
     __syncthreads();
   }
 #pragma unroll
   for (int j = 0; j < PB; ++j) G[j] = T(0);
   val = 0.0;
-  const T is2 = static_cast<T>(m.inv_sigma2);
+  qsum = 0.0;
+  // the chain's own 1/sigma_y^2 for the hierarchical Gaussian
+  const T is2 = FAM == FAM_HGAUSS ? static_cast<T>(exp(-2.0 * m.q1[(m.p + 2) * m.C + cc]))
+                                  : static_cast<T>(m.inv_sigma2);
+  T qacc = T(0);
   const int64_t r0 = wr[wave], r1 = wr[wave + 1];
   // Hierarchical: rows are sorted by group.  A group that starts and ends
   // inside this wave's rows is this wave's alone and goes straight to rg; the
@@ -126,7 +133,7 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
     T eta = T(0);
 #pragma unroll
     for (int j = 0; j < PB; ++j) eta += xv[j] * th[j];
-    if (FAM == FAM_HIER) {
+    if (hier_fam<FAM>()) {
       if (g != gcur) {
         if (gcur >= 0) {
           if (gfirst < 0) {
@@ -150,7 +157,8 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
     const T r = train ? vresid<FAM, T>(y, eta, is2) : T(0);
 #pragma unroll
     for (int j = 0; j < PB; ++j) G[j] += xv[j] * r;
-    if (FAM == FAM_HIER) racc += r;
+    if (hier_fam<FAM>()) racc += r;
+    if (FAM == FAM_HGAUSS) qacc += (y - eta) * r;
     if (VALUE && want_value) {
       if (train) val += static_cast<double>(vell0<FAM, T>(y, eta, is2));
     }
@@ -160,20 +168,20 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
     constexpr int FKR = decltype(fold_kind)::value;
     // GLM rows: four rows per trip puts their scalar loads under one wait.
     // The hierarchical row carries a group-change branch and gains nothing.
-    constexpr int RU = FAM == FAM_HIER ? 1 : 4;
+    constexpr int RU = hier_fam<FAM>() ? 1 : 4;
 #pragma unroll RU
     for (int64_t i = ra; i < rb; ++i) {
       const T* xr = Xv + i * PB;
       T xv[PB];
 #pragma unroll
       for (int j = 0; j < PB; ++j) xv[j] = xr[j];
-      row(fold_kind, i, xv, ValuY<T>::get(m, i), FAM == FAM_HIER ? m.group_of[i] : 0,
+      row(fold_kind, i, xv, ValuY<T>::get(m, i), hier_fam<FAM>() ? m.group_of[i] : 0,
           FKR == PCV_FOLDS_INDEX ? m.fold_index[i] : 0);
     }
   };
   if (m.fold_kind == PCV_FOLDS_INDEX) {
     rows(std::integral_constant<int, PCV_FOLDS_INDEX>{}, r0, r1);
-  } else if (m.fold_kind == PCV_FOLDS_INTERVALS && FAM == FAM_HIER) {
+  } else if (m.fold_kind == PCV_FOLDS_INTERVALS && hier_fam<FAM>()) {
     rows(std::integral_constant<int, PCV_FOLDS_INTERVALS>{}, r0, r1);
   } else if (m.fold_kind == PCV_FOLDS_INTERVALS) {
     // Interval folds exclude one contiguous row range per lane.  Outside the
@@ -197,7 +205,7 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
   } else {
     rows(std::integral_constant<int, PCV_FOLDS_DENSE>{}, r0, r1);
   }
-  if (FAM == FAM_HIER) {
+  if (hier_fam<FAM>()) {
     int glast = -1;
     if (gcur >= 0) {
       if (gfirst < 0) {
@@ -251,6 +259,16 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
     }
     __syncthreads();
   }
+  if (FAM == FAM_HGAUSS) {
+    vred[wave * 64 + lane] = static_cast<double>(qacc);
+    __syncthreads();
+    if (wave == 0) {
+      double s = 0.0;
+      for (int w = 0; w < W; ++w) s += vred[w * 64 + lane];
+      qsum = s;
+    }
+    __syncthreads();
+  }
 }
 
 // Wave 0, lane = chain: add the prior to the reduced likelihood gradient
@@ -258,30 +276,37 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
 // is deliberately not unrolled: unrolling hoists one address per coordinate
 // out of the leapfrog loop and exhausts the register file.
 template <typename T, int FAM, int PB, typename Emit>
-__device__ __forceinline__ void finish_chain(const DevModel& m, int64_t c, int lane, char* smem, int W, Emit emit) {
+__device__ __forceinline__ void finish_chain(const DevModel& m, int64_t c, int lane, char* smem, int W, double qsum,
+                                             Emit emit) {
   constexpr int JC = valu_jc<T, PB>();
   T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);
-  T* rg = zt + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
-  const T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
+  T* rg = zt + (hier_fam<FAM>() ? m.n_groups * 64 : 0);
+  const T* gfin = rg + (hier_fam<FAM>() ? m.n_groups * 64 : 0);
   const uint8_t* mrow = mask_row(m, c);
 #pragma nounroll
   for (int64_t j = 0; j < m.p; ++j)
     emit(j, (covariate_used(mrow, j) ? static_cast<double>(gfin[j * 64 + lane]) : 0.0) +
                 prior_grad(m, m.q1[j * m.C + c], j));
-  if (FAM == FAM_HIER) {
+  if (hier_fam<FAM>()) {
     const double u = m.q1[(m.p + 1) * m.C + c];
     const double tau = exp(u);
+    const int64_t z0 = hier_z0(m);
     double gmu = 0.0, gu = 0.0;
 #pragma nounroll
     for (int g = 0; g < m.n_groups; ++g) {
       const double rs = static_cast<double>(rg[g * 64 + lane]);
-      const double z = m.q1[(m.p + 2 + g) * m.C + c];
+      const double z = m.q1[(z0 + g) * m.C + c];
       gmu += rs;
       gu += z * rs;
-      emit(m.p + 2 + g, tau * rs - z);
+      emit(z0 + g, tau * rs - z);
     }
     emit(m.p, gmu - m.q1[m.p * m.C + c]);
     emit(m.p + 1, tau * gu + prior_grad(m, u, m.p + 1));
+    if (FAM == FAM_HGAUSS) {
+      // d/d log sigma_y of sum_train (-log sigma_y - (y - eta)^2 / (2 sigma_y^2))
+      const double uy = m.q1[(m.p + 2) * m.C + c];
+      emit(m.p + 2, qsum - m.ntrain[fold_of_chain(m, c)] + prior_grad(m, uy, m.p + 2));
+    }
   }
 }
 
@@ -303,7 +328,7 @@ __device__ __forceinline__ void finish_chain(const DevModel& m, int64_t c, int l
     ehi = m.ivals[4 * k + 3];                                                  \
   }                                                                            \
   T G[PB];                                                                     \
-  double val;                                                                  \
+  double val, qsum;                                                            \
   const bool lead = (wave == 0) && valid;
 
 constexpr int VALU_MAX_THREADS = 512;
@@ -312,9 +337,9 @@ constexpr int VALU_MAX_THREADS = 512;
 template <typename T, int FAM, int PB>
 __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_grad(ValuArgs a) {
   VALU_PROLOGUE
-  grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem);
+  grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem);
   if (lead) {
-    finish_chain<T, FAM, PB>(m, c, lane, smem, W, [&](int64_t j, double g) { m.g1[j * m.C + c] = g; });
+    finish_chain<T, FAM, PB>(m, c, lane, smem, W, qsum, [&](int64_t j, double g) { m.g1[j * m.C + c] = g; });
     m.logp1[c] = val + m.fold_const[k] + prior_quad(m, m.q1, c);
   }
 }
@@ -324,9 +349,9 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_grad(ValuArgs a) {
 template <typename T, int FAM, int PB>
 __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_leap(ValuArgs a) {
   VALU_PROLOGUE
-  grad_eval<T, FAM, PB, false>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem);
+  grad_eval<T, FAM, PB, false>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem);
   if (lead) {
-    finish_chain<T, FAM, PB>(m, c, lane, smem, W, [&](int64_t j, double g) {
+    finish_chain<T, FAM, PB>(m, c, lane, smem, W, qsum, [&](int64_t j, double g) {
       const int64_t o = j * m.C + c;
       const double p = m.pm[o] + 0.5 * m.eps * g;
       m.pm[o] = p;
@@ -336,9 +361,9 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_leap(ValuArgs a) {
   __syncthreads();
   for (int s = 0; s < a.n_steps; ++s) {
     const bool last = s == a.n_steps - 1;
-    grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem);
+    grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem);
     if (lead) {
-      finish_chain<T, FAM, PB>(m, c, lane, smem, W,
+      finish_chain<T, FAM, PB>(m, c, lane, smem, W, qsum,
                                [&](int64_t j, double g) { leapfrog_update(m, c, j, g, last); });
       if (last) m.logp1[c] = val + m.fold_const[k] + prior_quad(m, m.q1, c);
     }
@@ -356,9 +381,9 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_iter(ValuArgs a) {
     __syncthreads();
     for (int s = 0; s < m.S; ++s) {
       const bool last = s == m.S - 1;
-      grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem, last);
+      grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem, last);
       if (lead) {
-        finish_chain<T, FAM, PB>(m, c, lane, smem, W,
+        finish_chain<T, FAM, PB>(m, c, lane, smem, W, qsum,
                                  [&](int64_t j, double g) { leapfrog_update(m, c, j, g, last); });
         if (last) m.logp1[c] = val + m.fold_const[k] + prior_quad(m, m.q1, c);
       }
@@ -380,17 +405,18 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_part(ValuArgs a) {
   VALU_PROLOGUE
   const int sp = blockIdx.y;
   const int32_t* wr = m.wave_rows + static_cast<int64_t>(sp) * (W + 1);
-  if (a.value) grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem, true, wr);
-  else grad_eval<T, FAM, PB, false>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, smem, false, wr);
+  if (a.value) grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem, true, wr);
+  else grad_eval<T, FAM, PB, false>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem, false, wr);
   if (lead) {
     constexpr int JC = valu_jc<T, PB>();
     T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);
-    const T* rg = zt + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
-    const T* gfin = rg + (FAM == FAM_HIER ? m.n_groups * 64 : 0);
+    const T* rg = zt + (hier_fam<FAM>() ? m.n_groups * 64 : 0);
+    const T* gfin = rg + (hier_fam<FAM>() ? m.n_groups * 64 : 0);
     double* out = a.Gpart + static_cast<int64_t>(sp) * m.d * m.C + c;
 #pragma nounroll
     for (int64_t j = 0; j < m.p; ++j) out[j * m.C] = static_cast<double>(gfin[j * 64 + lane]);
-    if (FAM == FAM_HIER) {
+    if (hier_fam<FAM>()) {
+      const int64_t z0 = hier_z0(m);
       // group sums r_g of this split's groups only (the finish kernel reads
       // group g from the splits that span it), and the split's shares of the
       // mu and log tau likelihood gradients, sum_g r_g and sum_g z_g r_g
@@ -400,12 +426,13 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_part(ValuArgs a) {
 #pragma nounroll
       for (int g = glo; g <= ghi; ++g) {
         const double r = static_cast<double>(rg[g * 64 + lane]);
-        out[(m.p + 2 + g) * m.C] = r;
+        out[(z0 + g) * m.C] = r;
         sr += r;
-        szr += m.q1[(m.p + 2 + g) * m.C + c] * r;
+        szr += m.q1[(z0 + g) * m.C + c] * r;
       }
       out[m.p * m.C] = sr;
       out[(m.p + 1) * m.C] = szr;
+      if (FAM == FAM_HGAUSS) out[(m.p + 2) * m.C] = qsum;   // this split's sum of (y - eta)^2 / sigma_y^2
       if (sp == 0) a.uscr[c] = m.q1[(m.p + 1) * m.C + c];
     }
     if (a.value) a.Vpart[static_cast<int64_t>(sp) * m.C + c] = val;
@@ -427,8 +454,9 @@ __global__ void k_valu_finish(DevModel m, const double* __restrict__ Gpart, cons
   const int64_t j = idx / m.C, c = idx - j * m.C;
   const int64_t dC = m.d * m.C;
   int s0 = 0, s1 = ns - 1;
-  if (j >= m.p + 2) {
-    const int64_t g = j - m.p - 2;
+  const int64_t z0 = hier_z0(m);
+  if (j >= z0) {
+    const int64_t g = j - z0;
     s0 = m.gsplit[2 * g];
     s1 = m.gsplit[2 * g + 1];
   }
@@ -453,9 +481,13 @@ __global__ void k_valu_finish(DevModel m, const double* __restrict__ Gpart, cons
   for (; sp <= s1; ++sp) v += gp[sp * dC];
   double g;
   if (j < m.p) {
+    if (!covariate_used(mask_row(m, c), j)) v = 0.0;   // a masked coefficient: prior only
     g = v + prior_grad(m, m.q1[idx], j);
   } else if (j == m.p) {
     g = v - m.q1[idx];
+  } else if (m.family == FAM_HGAUSS && j == m.p + 2) {
+    // log sigma_y: sum_train (y - eta)^2 / sigma_y^2 - n_train + prior
+    g = v - m.ntrain[fold_of_chain(m, c)] + prior_grad(m, m.q1[idx], j);
   } else {
     const double u = uscr[c];
     const double tau = exp(u);
@@ -473,7 +505,7 @@ size_t valu_smem_bytes(bool fp64, int W, int family, int n_groups, int pb) {
   const size_t jc = std::min<size_t>(fp64 ? 4 : 8, static_cast<size_t>(pb));
   size_t b = tsz * W * jc * 64 + 8 * W * 64;
   b += tsz * static_cast<size_t>(pb) * 64;   // gfin
-  if (family == FAM_HIER) b += 2 * tsz * n_groups * 64 + 2 * tsz * W * 64 + 8 * W;   // zt, rg, edge slots
+  if (hier_family(family)) b += 2 * tsz * n_groups * 64 + 2 * tsz * W * 64 + 8 * W;   // zt, rg, edge slots
   return b;
 }
 
@@ -544,10 +576,12 @@ PCV_VALU_EXTERN(double, FAM_GAUSS)
 PCV_VALU_EXTERN(double, FAM_LOGIT)
 PCV_VALU_EXTERN(double, FAM_POIS)
 PCV_VALU_EXTERN(double, FAM_HIER)
+PCV_VALU_EXTERN(double, FAM_HGAUSS)
 PCV_VALU_EXTERN(float, FAM_GAUSS)
 PCV_VALU_EXTERN(float, FAM_LOGIT)
 PCV_VALU_EXTERN(float, FAM_POIS)
 PCV_VALU_EXTERN(float, FAM_HIER)
+PCV_VALU_EXTERN(float, FAM_HGAUSS)
 #undef PCV_VALU_EXTERN
 
 hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int mode, int64_t t0,
@@ -567,6 +601,7 @@ hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int
       case FAM_LOGIT: return launch_fam<double, FAM_LOGIT>(a, pb, W, st, smem, nblk, 1);
       case FAM_POIS: return launch_fam<double, FAM_POIS>(a, pb, W, st, smem, nblk, 1);
       case FAM_HIER: return launch_fam<double, FAM_HIER>(a, pb, W, st, smem, nblk, 1);
+      case FAM_HGAUSS: return launch_fam<double, FAM_HGAUSS>(a, pb, W, st, smem, nblk, 1);
     }
   } else {
     switch (m.family) {
@@ -574,6 +609,7 @@ hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int
       case FAM_LOGIT: return launch_fam<float, FAM_LOGIT>(a, pb, W, st, smem, nblk, 1);
       case FAM_POIS: return launch_fam<float, FAM_POIS>(a, pb, W, st, smem, nblk, 1);
       case FAM_HIER: return launch_fam<float, FAM_HIER>(a, pb, W, st, smem, nblk, 1);
+      case FAM_HGAUSS: return launch_fam<float, FAM_HGAUSS>(a, pb, W, st, smem, nblk, 1);
     }
   }
   return hipErrorInvalidValue;
@@ -597,6 +633,7 @@ hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb
       case FAM_LOGIT: return launch_fam<double, FAM_LOGIT>(a, pb, W, st, smem, nblk, ns);
       case FAM_POIS: return launch_fam<double, FAM_POIS>(a, pb, W, st, smem, nblk, ns);
       case FAM_HIER: return launch_fam<double, FAM_HIER>(a, pb, W, st, smem, nblk, ns);
+      case FAM_HGAUSS: return launch_fam<double, FAM_HGAUSS>(a, pb, W, st, smem, nblk, ns);
     }
   } else {
     switch (m.family) {
@@ -604,6 +641,7 @@ hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb
       case FAM_LOGIT: return launch_fam<float, FAM_LOGIT>(a, pb, W, st, smem, nblk, ns);
       case FAM_POIS: return launch_fam<float, FAM_POIS>(a, pb, W, st, smem, nblk, ns);
       case FAM_HIER: return launch_fam<float, FAM_HIER>(a, pb, W, st, smem, nblk, ns);
+      case FAM_HGAUSS: return launch_fam<float, FAM_HGAUSS>(a, pb, W, st, smem, nblk, ns);
     }
   }
   return hipErrorInvalidValue;
@@ -615,13 +653,14 @@ int valu_part_occupancy(bool fp64, int family, int pb, int W, size_t smem) {
     case FAM_LOGIT: return fp64 ? part_occupancy_fam<double, FAM_LOGIT>(pb, W, smem) : part_occupancy_fam<float, FAM_LOGIT>(pb, W, smem);
     case FAM_POIS: return fp64 ? part_occupancy_fam<double, FAM_POIS>(pb, W, smem) : part_occupancy_fam<float, FAM_POIS>(pb, W, smem);
     case FAM_HIER: return fp64 ? part_occupancy_fam<double, FAM_HIER>(pb, W, smem) : part_occupancy_fam<float, FAM_HIER>(pb, W, smem);
+    case FAM_HGAUSS: return fp64 ? part_occupancy_fam<double, FAM_HGAUSS>(pb, W, smem) : part_occupancy_fam<float, FAM_HGAUSS>(pb, W, smem);
   }
   return 0;
 }
 
 hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, const double* uscr, int ns, int mode,
                               hipStream_t st) {
-  if (m.family != FAM_HIER) return hipErrorInvalidValue;
+  if (!hier_family(m.family)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_valu_finish, dim3(static_cast<unsigned>((m.d * m.C + 255) / 256)), dim3(256), 0, st, m, Gpart,
                      uscr, ns, mode);
   return hipGetLastError();

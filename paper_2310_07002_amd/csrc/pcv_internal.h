@@ -62,6 +62,7 @@ struct DevModel {
   const double* minv;         // [d]
   const double* prior_prec;   // [d] 1/scale^2
   const double* fold_const;   // [K]
+  const double* ntrain;       // [K] training rows per fold (FAM_HGAUSS: the -n log sigma_y term)
   // chain state, [d][C] (chain index fastest)
   double *q0, *g0, *q1, *g1, *pm;
   double *logp0, *logp1, *s0, *h0;
@@ -130,18 +131,30 @@ __device__ __forceinline__ double log_add_exp(double a, double b) {
   return m + log1p(exp(-fabs(a - b)));
 }
 
-enum { FAM_GAUSS = 0, FAM_LOGIT = 1, FAM_POIS = 2, FAM_HIER = 3 };
+enum { FAM_GAUSS = 0, FAM_LOGIT = 1, FAM_POIS = 2, FAM_HIER = 3, FAM_HGAUSS = 4 };
+// Hierarchical families: theta = [beta (p), mu, log group scale, (log sigma_y,) z (groups)],
+// eta = x'beta + mu + e^{log group scale} z_g.  FAM_HIER: Bernoulli-logit;
+// FAM_HGAUSS: Gaussian with unknown noise sd sigma_y = e^{theta[p + 2]}.
+template <int FAM>
+__host__ __device__ constexpr bool hier_fam() { return FAM == FAM_HIER || FAM == FAM_HGAUSS; }
+__host__ __device__ constexpr bool hier_family(int fam) { return fam == FAM_HIER || fam == FAM_HGAUSS; }
+// variance of the half-normal priors of the two scales of FAM_HGAUSS
+constexpr double HGAUSS_SCALE_VAR = 10.0;
+// MFMA tile shapes of the matrix-core gradient kernel (a launch-shape knob)
+enum { MFMA_SHAPE_16X16X32 = 0, MFMA_SHAPE_32X32X16 = 1 };
 
 // d l(y, eta) / d eta and l(y, eta) minus its per-row constant.
+// (FAM_HGAUSS: the Gaussian forms with the chain's own 1/sigma_y^2; its
+// per-row -log sigma_y is added by the callers.)
 template <int FAM>
 __device__ __forceinline__ double resid64(double y, double eta, double inv_sigma2) {
-  if (FAM == FAM_GAUSS) return (y - eta) * inv_sigma2;
+  if (FAM == FAM_GAUSS || FAM == FAM_HGAUSS) return (y - eta) * inv_sigma2;
   if (FAM == FAM_POIS) return y - exp(eta);
   return y - 1.0 / (1.0 + exp(-eta));
 }
 template <int FAM>
 __device__ __forceinline__ double ell0_64(double y, double eta, double inv_sigma2) {
-  if (FAM == FAM_GAUSS) {
+  if (FAM == FAM_GAUSS || FAM == FAM_HGAUSS) {
     const double e = y - eta;
     return -0.5 * e * e * inv_sigma2;
   }
@@ -150,13 +163,13 @@ __device__ __forceinline__ double ell0_64(double y, double eta, double inv_sigma
 }
 template <int FAM>
 __device__ __forceinline__ float resid32(float y, float eta, float inv_sigma2) {
-  if (FAM == FAM_GAUSS) return (y - eta) * inv_sigma2;
+  if (FAM == FAM_GAUSS || FAM == FAM_HGAUSS) return (y - eta) * inv_sigma2;
   if (FAM == FAM_POIS) return y - __expf(eta);
   return y - 1.0f / (1.0f + __expf(-eta));
 }
 template <int FAM>
 __device__ __forceinline__ float ell0_32(float y, float eta, float inv_sigma2) {
-  if (FAM == FAM_GAUSS) {
+  if (FAM == FAM_GAUSS || FAM == FAM_HGAUSS) {
     const float e = y - eta;
     return -0.5f * e * e * inv_sigma2;
   }
@@ -168,6 +181,10 @@ __device__ __forceinline__ float ell0_32(float y, float eta, float inv_sigma2) {
 // of the covariate mask of its model (null with one model: every covariate
 // used).  Chain indices fit 32 bits (checked at init), so the divisions are
 // 32-bit; call these once per chain, outside loops over rows or covariates.
+// First z coordinate of the hierarchical families.
+__host__ __device__ __forceinline__ int64_t hier_z0(const DevModel& m) {
+  return m.p + (m.family == FAM_HGAUSS ? 3 : 2);
+}
 __host__ __device__ __forceinline__ int fold_of_chain(const DevModel& m, int64_t c) {
   const uint32_t post = static_cast<uint32_t>(c) / static_cast<uint32_t>(m.L);
   return static_cast<int>(m.M > 1 ? post % static_cast<uint32_t>(m.K) : post);
@@ -205,10 +222,10 @@ __device__ __forceinline__ double eta_row64(const DevModel& m, const double* q, 
   double e = 0.0;
   const uint8_t* mrow = mask_row(m, c);
   for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(mrow, j) ? q[j * m.C + c] : 0.0);
-  if (m.family == FAM_HIER) {
+  if (hier_family(m.family)) {
     const double mu = q[m.p * m.C + c];
     const double tau = exp(q[(m.p + 1) * m.C + c]);
-    e += mu + tau * q[(m.p + 2 + m.group_of[i]) * m.C + c];
+    e += mu + tau * q[(hier_z0(m) + m.group_of[i]) * m.C + c];
   }
   return e;
 }
@@ -217,10 +234,15 @@ __device__ __forceinline__ double eta_row64(const DevModel& m, const double* q, 
 // fold at q; the group location and scale are read once.
 template <int FAM>
 __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, int a0, int a1) {
-  double mu = 0.0, tau = 0.0;
-  if (FAM == FAM_HIER) {
+  double mu = 0.0, tau = 0.0, is2 = m.inv_sigma2, lsy = 0.0;
+  const int64_t z0 = hier_z0(m);
+  if (hier_fam<FAM>()) {
     mu = q[m.p * m.C + c];
     tau = exp(q[(m.p + 1) * m.C + c]);
+  }
+  if (FAM == FAM_HGAUSS) {
+    lsy = q[(m.p + 2) * m.C + c];
+    is2 = exp(-2.0 * lsy);
   }
   const uint8_t* mrow = mask_row(m, c);
   double s = 0.0;
@@ -235,8 +257,8 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
       const double* x = m.X64 + i * m.p;
       double e = 0.0;
       for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(mrow, j) ? q[j * m.C + c] : 0.0);
-      if (FAM == FAM_HIER) e += mu + tau * q[(m.p + 2 + m.group_of[i]) * m.C + c];
-      s += ell0_64<FAM>(m.y64[i], e, m.inv_sigma2) + m.rowc[i];
+      if (hier_fam<FAM>()) e += mu + tau * q[(z0 + m.group_of[i]) * m.C + c];
+      s += ell0_64<FAM>(m.y64[i], e, is2) + m.rowc[i] - lsy;
       break;
     }
     int64_t i[4];
@@ -265,8 +287,8 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (t + u < a1) {
-        if (FAM == FAM_HIER) e[u] += mu + tau * q[(m.p + 2 + m.group_of[i[u]]) * m.C + c];
-        s += ell0_64<FAM>(m.y64[i[u]], e[u], m.inv_sigma2) + m.rowc[i[u]];
+        if (hier_fam<FAM>()) e[u] += mu + tau * q[(z0 + m.group_of[i[u]]) * m.C + c];
+        s += ell0_64<FAM>(m.y64[i[u]], e[u], is2) + m.rowc[i[u]] - lsy;
       }
     }
   }
@@ -280,9 +302,34 @@ __device__ double log_pred_fold(const DevModel& m, const double* q, int64_t c) {
   return log_pred_rows<FAM>(m, q, c, m.test_ptr[k], m.test_ptr[k + 1]);
 }
 
-// Prior: returns the non-constant part of log prior at q (constants are in fold_const).
+// Coordinate j's share of prior_quad at value t.
+__device__ __forceinline__ double prior_term(const DevModel& m, double t, int64_t j) {
+  if (m.family == FAM_HGAUSS) {
+    if (j == m.p + 1 || j == m.p + 2) return -0.5 * exp(2.0 * t) / HGAUSS_SCALE_VAR + t;
+    return -0.5 * t * t;
+  }
+  if (m.family == FAM_HIER) {
+    if (j == m.p + 1) {
+      const double tau = exp(t);
+      return -0.5 * tau * tau + t;
+    }
+    return -0.5 * t * t;
+  }
+  return -0.5 * t * t * m.prior_prec[j];
+}
+
+// Prior: returns the non-constant part of log prior at q (constants are in
+// fold_const).  For FAM_HGAUSS it also carries the likelihood's chain-dependent
+// normalisation, -n_train(k) log sigma_y.
 __device__ __forceinline__ double prior_quad(const DevModel& m, const double* q, int64_t c) {
   double v = 0.0;
+  if (m.family == FAM_HGAUSS) {
+    // beta, mu, z ~ N(0, 1); sigma_a, sigma_y half-normal (variance 10) with
+    // the log-Jacobians; plus the likelihood's -n_train log sigma_y
+    for (int64_t j = 0; j < m.d; ++j) v += prior_term(m, q[j * m.C + c], j);
+    v -= m.ntrain[fold_of_chain(m, c)] * q[(m.p + 2) * m.C + c];
+    return v;
+  }
   if (m.family == FAM_HIER) {
     for (int64_t j = 0; j < m.d; ++j) {
       if (j == m.p + 1) continue;
@@ -301,19 +348,11 @@ __device__ __forceinline__ double prior_quad(const DevModel& m, const double* q,
   return v;
 }
 
-// Coordinate j's share of prior_quad at value t.
-__device__ __forceinline__ double prior_term(const DevModel& m, double t, int64_t j) {
-  if (m.family == FAM_HIER) {
-    if (j == m.p + 1) {
-      const double tau = exp(t);
-      return -0.5 * tau * tau + t;
-    }
-    return -0.5 * t * t;
-  }
-  return -0.5 * t * t * m.prior_prec[j];
-}
-
 __device__ __forceinline__ double prior_grad(const DevModel& m, double theta, int64_t j) {
+  if (m.family == FAM_HGAUSS) {
+    if (j == m.p + 1 || j == m.p + 2) return -exp(2.0 * theta) / HGAUSS_SCALE_VAR + 1.0;
+    return -theta;
+  }
   if (m.family == FAM_HIER) {
     if (j == m.p + 1) return -exp(2.0 * theta) + 1.0;
     return -theta;
@@ -422,6 +461,7 @@ __device__ double predictive_draw(const DevModel& m, double eta, W4 w) {
 // HS and DSS sums of one post-warm-up draw at the accepted state q0.
 template <int FAM>
 __device__ void accumulate_scores(const DevModel& m, int64_t c, int64_t t) {
+  if (FAM == FAM_HGAUSS) return;   // pcv_init refuses HS / DSS for this family
   const int k = fold_of_chain(m, c);
   const int64_t l = c % m.L;
   const int beg = m.test_ptr[k], v = m.test_ptr[k + 1] - beg;

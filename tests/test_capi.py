@@ -86,8 +86,9 @@ def test_unsupported_shapes_are_reported():
 
 
 def test_model_masks_are_validated():
-    """Several models in one launch: masks must be 0/1 and present; the
-    hierarchical family and the scores are refused (host checks, no device)."""
+    """Several models in one launch: masks must be 0/1 and present; scores
+    are refused, and hierarchical families off the fp64 / fp32 paths (host
+    checks, no device)."""
     w = W.fold_subset(W.make("c1"), 0, 3)
     m = np.ones((2, w.p), dtype=np.uint8)
     w2 = W.with_models(w, m)
@@ -97,7 +98,11 @@ def test_model_masks_are_validated():
     h = W.fold_subset(W.make("c2"), 0, 2)
     h2 = dataclasses.replace(h, n_models=2, model_mask=np.ones((2, h.p), dtype=np.uint8),
                              init_pos=np.concatenate([h.init_pos] * 2))
-    assert _expect_invalid(h2) == 5
+    assert _expect_invalid(h2, precision=W.PREC_BF16X3) == 5
+    e = W.make_ex1_ab()
+    assert _expect_invalid(e, precision=W.PREC_BF16X3) == 5
+    assert _expect_invalid(e, scores=2) == 5
+    assert _expect_invalid(W.make_ex1(), scores=1) == 5
 
 
 def test_init_positions_rejects_bad_arguments():

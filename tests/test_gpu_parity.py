@@ -112,6 +112,59 @@ def test_ragged_chain_tile_and_row_tail(dev):
     assert _normwise(g.cpu().numpy(), g_o).max() < 1e-5
 
 
+def _intervals_of_blocks(w, h):
+    """The blocked folds of w in the interval encoding, with h excluded rows
+    on each side of every test block."""
+    iv = np.zeros((w.K, 4), dtype=np.int64)
+    for k in range(w.K):
+        rows = np.flatnonzero(w.fold_index == k)
+        lo, hi = int(rows.min()), int(rows.max()) + 1
+        assert hi - lo == rows.size               # blocked folds are contiguous
+        iv[k] = (lo, hi, max(0, lo - h), min(w.n, hi + h))
+    return dataclasses.replace(w, fold_kind=W.FOLDS_INTERVALS, intervals=iv, fold_index=None)
+
+
+SHAPE_CASES = [
+    # (label, workload builder, precision, tol_v, tol_g)
+    ("c4-index", lambda: W.fold_subset(W.make("c4"), 0, 16), "bf16x3", 1e-5, 5e-5),
+    ("c4-index", lambda: W.fold_subset(W.make("c4"), 0, 16), "bf16x5", 1e-5, 1e-5),
+    ("c5-index", lambda: W.fold_subset(W.make("c5"), 100, 140), "bf16x3", 1e-5, 5e-5),
+    ("c5-intervals", lambda: _intervals_of_blocks(W.fold_subset(W.make("c5"), 100, 140), 7), "bf16x3", 1e-5, 5e-5),
+    ("c5-intervals", lambda: _intervals_of_blocks(W.fold_subset(W.make("c5"), 100, 140), 7), "bf16x5", 1e-5, 1e-5),
+    ("c4-ragged", lambda: (lambda w: dataclasses.replace(w, X=w.X[:19990], y=w.y[:19990],
+                                                         fold_index=w.fold_index[:19990]))(
+        W.fold_subset(W.make("c4"), 3, 40)), "bf16x3", 1e-5, 5e-5),
+]
+
+
+@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("label,make_w,prec,tol_v,tol_g", SHAPE_CASES)
+def test_mfma_tile_shapes_match_oracle(dev, shape, label, make_w, prec, tol_v, tol_g):
+    """Both MFMA tile shapes of the matrix-core kernel (16x16x32 and 32x32x16
+    bf16 products) at several row-split counts: value and gradient against the
+    oracle, index and interval folds, a ragged chain tile and row tail."""
+    w = make_w()
+    theta = _theta_near_init(w, seed=7)
+    lp_o, g_o = _oracle_eval(w, theta)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    n_tiles = (w.n + 31) // 32
+    for ns in (1, 7, min(64, n_tiles)):
+        s.set_launch_config(256 * shape + ns)
+        cfg = s.launch_config()
+        assert cfg // 256 == shape
+        lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+        rel_v = np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)
+        rel_g = _normwise(g.cpu().numpy(), g_o)
+        _say(f"[shape {shape}] {label} {prec} C={w.C} n={w.n} config {cfg}: logp rel max {rel_v.max():.2e}  "
+             f"grad normwise max {rel_g.max():.2e}")
+        assert rel_v.max() < tol_v
+        assert rel_g.max() < tol_g
+    with pytest.raises(binding.PcvError):
+        s.set_launch_config(256 * 2 + 1)
+    assert s.launch_config() == cfg
+    s.close()
+
+
 @pytest.mark.parametrize("prec,tol_v,tol_g", [("bf16x3", 1e-5, 5e-5), ("bf16x5", 1e-5, 1e-5)])
 def test_interval_folds_on_matrix_cores(dev, prec, tol_v, tol_g):
     """hv-block style folds (test block plus a buffer of h rows each side,
@@ -613,14 +666,18 @@ def test_checkpoint_guards_the_target_and_carries_the_tuning(dev, tmp_path):
     _say(f"[checkpoint] adapted eps {r['step_size']:.4f} resumed bit for bit")
 
 
-@pytest.mark.parametrize("name,prec,tol_g", [("c5", "bf16x3", 5e-5), ("c4", "bf16x3", 5e-5), ("c5", "bf16x5", 1e-5)])
-def test_full_size_sampled_parity(dev, name, prec, tol_g):
+@pytest.mark.parametrize("name,prec,tol_v,tol_g", [("c5", "bf16x3", 1e-5, 5e-5), ("c4", "bf16x3", 1e-5, 5e-5),
+                                                   ("c5", "bf16x5", 1e-5, 1e-5), ("c3", "fp64", 1e-12, 1e-12)])
+def test_full_size_sampled_parity(dev, name, prec, tol_v, tol_g):
     """The full configuration in the launch shape the benchmark times (all
-    chains, all row splits), checked on sampled folds one at a time."""
+    chains, all row splits, the autotuned split count), checked on sampled
+    folds one at a time."""
     w = W.make(name)
     _say(f"[full size] {name} {prec} C={w.C}")
     theta = _theta_near_init(w, seed=11)
     s = binding.PCV.from_workload(w, precision=PREC[prec])
+    tune = s.autotune()
+    _say(f"    autotuned launch shape {tune['config']}")
     lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
     lp, g = lp.cpu().numpy(), g.cpu().numpy()
     assert np.all(np.isfinite(lp)) and np.all(np.isfinite(g))
@@ -633,8 +690,31 @@ def test_full_size_sampled_parity(dev, name, prec, tol_g):
         worst_v = max(worst_v, float(np.max(np.abs(lp[sl] - lp_o) / np.abs(lp_o))))
         worst_g = max(worst_g, float(np.max(_normwise(g[sl], g_o))))
     _say(f"    sampled folds: logp rel max {worst_v:.2e}  grad normwise max {worst_g:.2e}")
-    assert worst_v < 1e-5
+    assert worst_v < tol_v
     assert worst_g < tol_g
+
+
+def test_hvblock_elpd_within_mcse_of_closed_form(dev):
+    """The full hv-block configuration (1000 folds x 8 chains, the autotuned
+    launch shape): the device's elpd lies within 4 MCSE of the sum of the
+    exact hv-block predictive densities (conjugate Gaussian, known sigma), and
+    per fold within 4 MCSE but for the few folds that chance allows."""
+    w = W.make("c3")
+    s = binding.PCV.from_workload(w)
+    s.autotune()
+    s.step(w.n_iter)
+    d = s.diagnostics()
+    e = s.elpd()
+    elpd_k, mcse_k = e["elpd_fold"], e["mcse_fold"]
+    roles = folds.roles_of(w)
+    exact_k = np.array([closed_form.fold_exact(w.X, w.y, w.sigma, w.prior_scale, roles[k] == 1,
+                                               roles[k] == 2)["elpd"] for k in range(w.K)])
+    z = np.abs(elpd_k - exact_k) / mcse_k
+    _say(f"[c3 full] elpd {d['elpd']:.4f} exact {exact_k.sum():.4f} mcse {d['mcse']:.4f} "
+         f"rhat_max {d['rhat_max']:.4f}; folds beyond 4 MCSE: {int(np.sum(z > 4))} of {w.K}, max z {z.max():.2f}")
+    assert d["n_draws"] == w.n_samples
+    assert abs(d["elpd"] - exact_k.sum()) < 4 * d["mcse"]
+    assert np.sum(z > 4) <= 2 and z.max() < 6
 
 
 @pytest.mark.parametrize("name,folds_,prec", [("c4", (0, 40), "bf16x3"), ("c3", (0, 40), "fp64"),
