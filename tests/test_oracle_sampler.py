@@ -148,3 +148,23 @@ def test_shifted_sums_mode_matches_welford_and_two_pass():
     _, rep_s = diagnostics.shuffle_benchmark(run.acc, w.K, w.L, D, 20, seed=3)
     _, rep_w = diagnostics.shuffle_benchmark(wf.acc, w.K, w.L, D, 20, seed=3)
     np.testing.assert_allclose(rep_s, rep_w, rtol=1e-9)
+
+
+def test_hvblock_elpd_within_mcse_of_closed_form():
+    """hv-block folds (v = 5 test rows, h = 10 excluded on each side) of the
+    conjugate AR(4) regression: the oracle's run on 6 folds (100 warm-up and
+    600 sampling transitions) lies within Monte Carlo error of the exact joint
+    predictive density of each fold's test block (Section 2, hv-block CV;
+    Gaussian closed form)."""
+    w = dataclasses.replace(W.fold_subset(W.make_c3(), 100, 106), n_warmup=100, n_samples=600)
+    run = sampler.run_all(w)
+    on = diagnostics.from_accumulators(run.acc, w.K, w.L, w.batch_size)
+    roles = folds.roles_of(w)
+    assert np.all((roles == folds.ROLE_TEST).sum(axis=1) == 5)
+    assert np.all((roles == folds.ROLE_EXCLUDED).sum(axis=1) == 20)
+    exact = np.array([closed_form.fold_exact(w.X, w.y, w.sigma, w.prior_scale,
+                                             roles[k] == 1, roles[k] == 2)["elpd"]
+                      for k in range(w.K)])
+    assert abs(on["elpd"] - exact.sum()) < 4 * on["mcse"]
+    z = (on["elpd_fold"] - exact) / on["mcse_fold"]
+    assert np.max(np.abs(z)) < 4.5
