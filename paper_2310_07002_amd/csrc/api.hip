@@ -70,7 +70,7 @@ struct pcv_ctx_s {
   int32_t* wave_rows = nullptr;
   // MFMA
   uint4* Xpk = nullptr;            // X packed for the current MFMA shape
-  uint4* Xpk_shape[2] = {nullptr, nullptr};   // packed X of each shape (made on first use)
+  uint4* Xpk_shape[2] = {nullptr, nullptr};   // packed X per fragment layout (made on first use)
   int mshape = MFMA_SHAPE_32X32X16;
   uint32_t* tflag = nullptr;       // [n_tiles][chain tiles] waves with a non-train or padded row
   float* ty = nullptr;
@@ -483,17 +483,18 @@ namespace {
 // MFMA path: switch the gradient kernel's tile shape, packing X for it on
 // first use (the fp64 design stays resident for that).
 pcv_status apply_mfma_shape(pcv_ctx ctx, int shape) {
-  if (shape != MFMA_SHAPE_16X16X32 && shape != MFMA_SHAPE_32X32X16)
+  if (shape < MFMA_SHAPE_16X16X32 || shape > MFMA_SHAPE_32X32X16_IL)
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown MFMA shape");
-  if (!ctx->Xpk_shape[shape]) {
+  const int layout = shape == MFMA_SHAPE_16X16X32 ? 0 : 1;   // both 32x32x16 kernels share a packing
+  if (!ctx->Xpk_shape[layout]) {
     const int P = static_cast<int>(ctx->m.p);
     const size_t nfr = static_cast<size_t>(ctx->n_tiles) * mfma_nfrag(P, shape) * 64;
     uint4* xp;
     TRY(dalloc(ctx, &xp, nfr));
     CK(launch_mfma_pack(ctx->m.X64, ctx->m.n, P, ctx->n_tiles, shape, xp, ctx->st));
-    ctx->Xpk_shape[shape] = xp;
+    ctx->Xpk_shape[layout] = xp;
   }
-  ctx->Xpk = ctx->Xpk_shape[shape];
+  ctx->Xpk = ctx->Xpk_shape[layout];
   ctx->mshape = shape;
   drop_graph(ctx);
   return PCV_OK;
@@ -1820,7 +1821,7 @@ pcv_status apply_splits(pcv_ctx ctx, int ns) {
 constexpr int MFMA_CFG_SHAPE = 256;
 bool mfma_cfg_ok(pcv_ctx ctx, int cfg) {
   const int shape = cfg / MFMA_CFG_SHAPE, ns = cfg % MFMA_CFG_SHAPE;
-  return cfg >= 0 && (shape == MFMA_SHAPE_16X16X32 || shape == MFMA_SHAPE_32X32X16) && ns >= 1 &&
+  return cfg >= 0 && shape >= MFMA_SHAPE_16X16X32 && shape <= MFMA_SHAPE_32X32X16_IL && ns >= 1 &&
          ns <= std::min(64, ctx->n_tiles);
 }
 pcv_status apply_mfma_cfg(pcv_ctx ctx, int cfg) {
@@ -1907,7 +1908,7 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
     // both MFMA tile shapes, each with row-split counts around the analytic
     // choice: config = MFMA_CFG_SHAPE * shape + splits
     const int ns0 = ctx->n_splits, hi = std::min(64, ctx->n_tiles);
-    for (int shape : {MFMA_SHAPE_32X32X16, MFMA_SHAPE_16X16X32})
+    for (int shape : {MFMA_SHAPE_32X32X16, MFMA_SHAPE_32X32X16_IL, MFMA_SHAPE_16X16X32})
       for (int ns : {ns0 / 2, ns0 - 2, ns0 - 1, ns0, ns0 + 1, ns0 + 2, 2 * ns0}) {
         if (ns < 1 || ns > hi) continue;
         const int tps = (ctx->n_tiles + ns - 1) / ns;
@@ -2139,6 +2140,8 @@ pcv_status pcv_timing_read(pcv_ctx ctx, double* ms_sum, int64_t* n_launches, con
   if (kernel_name)
     *kernel_name = ctx->path == PATH_MFMA && ctx->mshape == MFMA_SHAPE_32X32X16
                        ? "k_mfma32 (bf16 split 32x32x16 MFMA value+gradient)"
+                   : ctx->path == PATH_MFMA && ctx->mshape == MFMA_SHAPE_32X32X16_IL
+                       ? "k_mfma32 (bf16 split 32x32x16 MFMA value+gradient, free schedule)"
                        : kGradKernelName[ctx->path];
   if (reset) {
     ctx->ms_acc = 0.0;

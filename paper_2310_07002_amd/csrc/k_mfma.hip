@@ -476,7 +476,12 @@ __device__ __forceinline__ void m2_split2(float r0, float r1, uint32_t& hi, uint
   lo = __builtin_bit_cast(uint32_t, l);
 }
 
-template <int FAM, int P, int FWD, bool VALUE, int FK>
+// SCHED = 0 pins each group (its MFMAs, fragment reads and epilogue pair)
+// in program order; SCHED = 1 leaves the order of the tile's instructions to
+// the compiler, which may interleave the independent MFMA chains of
+// neighbouring groups (a forward and an adjoint group never depend on each
+// other).
+template <int FAM, int P, int FWD, bool VALUE, int FK, int SCHED>
 __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
   constexpr int KB = P / 16;                 // forward K blocks
   constexpr int MB = P / 32;                 // adjoint M blocks
@@ -486,6 +491,9 @@ __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
   constexpr int NT = FWD == 5 ? 3 : 2;
   constexpr int NBUF = 4;
   constexpr int NG = KB + 2 * MB;            // MFMA groups per tile: forward K blocks, adjoint (M block, K half)
+  // LDS fragment reads run PF groups ahead of their MFMAs (two where the
+  // registers allow it: the p = 128 kernels need theirs for operands)
+  constexpr int PF = P == 64 ? 2 : 1;
   static_assert(NST * 64 * MF_WAVES == NF * 64, "staging must tile the fragments");
   static_assert(NST == 2 || NST == 4, "two or four staged vectors per thread");
   static_assert(NG == 8 || NG == 16, "8 or 16 groups per tile");
@@ -646,15 +654,22 @@ __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
     f32x4 yq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) yq[q] = *reinterpret_cast<const f32x4*>(&sy[bc][8 * q + 4 * hh]);
-    bf16x8 xa0 = frag(b1, group_frag_index(0)), xa1 = frag(b1, group_frag_index(0) + 1);
+    // fragments of groups g .. g + PF are in flight (ring of PF + 1 groups)
+    bf16x8 xr0[PF + 1], xr1[PF + 1];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int bn = (q & 1) ? bp : b1;
+      xr0[q] = frag(bn, group_frag_index(q));
+      xr1[q] = frag(bn, group_frag_index(q) + 1);
+    }
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      bf16x8 xb0 = xa0, xb1 = xa1;
-      if (g + 1 < NG) {
-        const int bn = ((g + 1) & 1) ? bp : b1;
-        xb0 = frag(bn, group_frag_index(g + 1));
-        xb1 = frag(bn, group_frag_index(g + 1) + 1);
+      if (g + PF < NG) {
+        const int bn = ((g + PF) & 1) ? bp : b1;
+        xr0[(g + PF) % (PF + 1)] = frag(bn, group_frag_index(g + PF));
+        xr1[(g + PF) % (PF + 1)] = frag(bn, group_frag_index(g + PF) + 1);
       }
+      const bf16x8 xa0 = xr0[g % (PF + 1)], xa1 = xr1[g % (PF + 1)];
       if ((g & 1) == 0) {
         const int kb = g >> 1;
         f32x16 acc = eta_nxt;
@@ -704,9 +719,7 @@ __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
         rch[kh][w] = hw;
         rcl[kh][w] = lw;
       }
-      __builtin_amdgcn_sched_barrier(0);
-      xa0 = xb0;
-      xa1 = xb1;
+      if constexpr (SCHED == 0) __builtin_amdgcn_sched_barrier(0);
     }
     if (!VALUE && masked) {
       // this wave's chains have non-train (or padded) rows in the tile:
@@ -852,17 +865,18 @@ __global__ void k_mfma_pack(const double* __restrict__ X, int64_t n, int P, int 
 template <int FAM, int P, int FWD, int SHAPE>
 static hipError_t launch_mfma_p(const MfmaArgs& a, bool value, int nblk, hipStream_t st) {
   const bool iv = a.m.fold_kind == PCV_FOLDS_INTERVALS;
-#define PCV_MFMA_LAUNCH(KERN)                                                                              \
+#define PCV_MFMA_LAUNCH(KERN, ...)                                                                         \
   do {                                                                                                   \
     if (value) {                                                                                         \
-      if (iv) hipLaunchKernelGGL((KERN<FAM, P, FWD, true, PCV_FOLDS_INTERVALS>), dim3(nblk), dim3(512), 0, st, a); \
-      else hipLaunchKernelGGL((KERN<FAM, P, FWD, true, PCV_FOLDS_INDEX>), dim3(nblk), dim3(512), 0, st, a);       \
+      if (iv) hipLaunchKernelGGL((KERN<FAM, P, FWD, true, PCV_FOLDS_INTERVALS __VA_ARGS__>), dim3(nblk), dim3(512), 0, st, a); \
+      else hipLaunchKernelGGL((KERN<FAM, P, FWD, true, PCV_FOLDS_INDEX __VA_ARGS__>), dim3(nblk), dim3(512), 0, st, a);       \
     } else {                                                                                             \
-      if (iv) hipLaunchKernelGGL((KERN<FAM, P, FWD, false, PCV_FOLDS_INTERVALS>), dim3(nblk), dim3(512), 0, st, a); \
-      else hipLaunchKernelGGL((KERN<FAM, P, FWD, false, PCV_FOLDS_INDEX>), dim3(nblk), dim3(512), 0, st, a);       \
+      if (iv) hipLaunchKernelGGL((KERN<FAM, P, FWD, false, PCV_FOLDS_INTERVALS __VA_ARGS__>), dim3(nblk), dim3(512), 0, st, a); \
+      else hipLaunchKernelGGL((KERN<FAM, P, FWD, false, PCV_FOLDS_INDEX __VA_ARGS__>), dim3(nblk), dim3(512), 0, st, a);       \
     }                                                                                                    \
   } while (0)
-  if (SHAPE == MFMA_SHAPE_32X32X16) PCV_MFMA_LAUNCH(k_mfma32);
+  if (SHAPE == MFMA_SHAPE_32X32X16) PCV_MFMA_LAUNCH(k_mfma32, , 0);
+  else if (SHAPE == MFMA_SHAPE_32X32X16_IL) PCV_MFMA_LAUNCH(k_mfma32, , 1);
   else PCV_MFMA_LAUNCH(k_mfma);
 #undef PCV_MFMA_LAUNCH
   return hipGetLastError();
@@ -905,18 +919,19 @@ hipError_t launch_mfma(const DevModel& m, int shape, const uint4* Xpk, const flo
   const int nblk = n_ct * n_splits;
   const int P = static_cast<int>(m.p);
   if (shape == MFMA_SHAPE_32X32X16) return launch_mfma_s<MFMA_SHAPE_32X32X16>(a, P, fwd, value, nblk, st);
+  if (shape == MFMA_SHAPE_32X32X16_IL) return launch_mfma_s<MFMA_SHAPE_32X32X16_IL>(a, P, fwd, value, nblk, st);
   if (shape == MFMA_SHAPE_16X16X32) return launch_mfma_s<MFMA_SHAPE_16X16X32>(a, P, fwd, value, nblk, st);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_mfma_pack(const double* X, int64_t n, int P, int n_tiles, int shape, uint4* out, hipStream_t st) {
-  if (shape == MFMA_SHAPE_32X32X16) hipLaunchKernelGGL(k_mfma32_pack, dim3(1024), dim3(256), 0, st, X, n, P, n_tiles, out);
+  if (shape != MFMA_SHAPE_16X16X32) hipLaunchKernelGGL(k_mfma32_pack, dim3(1024), dim3(256), 0, st, X, n, P, n_tiles, out);
   else hipLaunchKernelGGL(k_mfma_pack, dim3(1024), dim3(256), 0, st, X, n, P, n_tiles, out);
   return hipGetLastError();
 }
 
 int mfma_chain_tile() { return MF_CHAIN_TILE; }
 int mfma_rows_per_tile() { return MF_ROWS; }
-int mfma_nfrag(int P, int shape) { return shape == MFMA_SHAPE_32X32X16 ? m2_nfrag(P) : mf_nfrag(P); }
+int mfma_nfrag(int P, int shape) { return shape != MFMA_SHAPE_16X16X32 ? m2_nfrag(P) : mf_nfrag(P); }
 
 }  // namespace pcv

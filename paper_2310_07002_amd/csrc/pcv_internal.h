@@ -141,7 +141,8 @@ __host__ __device__ constexpr bool hier_family(int fam) { return fam == FAM_HIER
 // variance of the half-normal priors of the two scales of FAM_HGAUSS
 constexpr double HGAUSS_SCALE_VAR = 10.0;
 // MFMA tile shapes of the matrix-core gradient kernel (a launch-shape knob)
-enum { MFMA_SHAPE_16X16X32 = 0, MFMA_SHAPE_32X32X16 = 1 };
+// (MFMA_SHAPE_32X32X16_IL: the 32x32x16 kernel scheduled by the compiler across groups)
+enum { MFMA_SHAPE_16X16X32 = 0, MFMA_SHAPE_32X32X16 = 1, MFMA_SHAPE_32X32X16_IL = 2 };
 
 // d l(y, eta) / d eta and l(y, eta) minus its per-row constant.
 // (FAM_HGAUSS: the Gaussian forms with the chain's own 1/sigma_y^2; its
