@@ -162,6 +162,9 @@ def main():
                     help="skip the second metric (wall time from init to R-hat_max < 1.01 at a batch end)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the analytic launch shape instead of timing candidates first")
+    ap.add_argument("--launch-config", type=int, default=None,
+                    help="apply this launch shape (pcv_autotune's encoding) instead of tuning, "
+                         "e.g. to profile the shape a full run chose")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device-to-device copy first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -193,7 +196,10 @@ def main():
     wt = dataclasses.replace(w, n_warmup=args.warmup)
     s = binding.PCV.from_workload(wt, precision=PREC_NAMES[prec], stream=stream)
     tune = None
-    if not args.no_autotune and prec != "fp64u":
+    if args.launch_config is not None:
+        s.set_launch_config(args.launch_config)
+        log(f"bench: launch config {args.launch_config} applied")
+    elif not args.no_autotune and prec != "fp64u":
         torch.cuda.synchronize()
         ta = time.perf_counter()
         tune = s.autotune()
@@ -299,7 +305,9 @@ def main():
     if not args.no_time_to_rhat:
         log("bench: full run for wall time to Rhat_max < 1.01")
         r = binding.PCV.from_workload(w, precision=PREC_NAMES[prec], stream=stream)
-        if tune is not None:
+        if args.launch_config is not None:
+            r.set_launch_config(args.launch_config)
+        elif tune is not None:
             r.autotune()              # tuning is reported separately, outside the clock
         torch.cuda.synchronize()
         t0 = time.perf_counter()

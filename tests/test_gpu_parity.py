@@ -137,12 +137,13 @@ SHAPE_CASES = [
 ]
 
 
-@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 @pytest.mark.parametrize("label,make_w,prec,tol_v,tol_g", SHAPE_CASES)
 def test_mfma_tile_shapes_match_oracle(dev, shape, label, make_w, prec, tol_v, tol_g):
-    """Both MFMA tile shapes of the matrix-core kernel (16x16x32 and 32x32x16
-    bf16 products) at several row-split counts: value and gradient against the
-    oracle, index and interval folds, a ragged chain tile and row tail."""
+    """Every launch shape of the matrix-core kernel (16x16x32 tiles; 32x32x16
+    tiles in program order or scheduled by the compiler) at several row-split
+    counts: value and gradient against the oracle, index and interval folds,
+    a ragged chain tile and row tail."""
     w = make_w()
     theta = _theta_near_init(w, seed=7)
     lp_o, g_o = _oracle_eval(w, theta)
@@ -160,7 +161,7 @@ def test_mfma_tile_shapes_match_oracle(dev, shape, label, make_w, prec, tol_v, t
         assert rel_v.max() < tol_v
         assert rel_g.max() < tol_g
     with pytest.raises(binding.PcvError):
-        s.set_launch_config(256 * 2 + 1)
+        s.set_launch_config(256 * 3 + 1)
     assert s.launch_config() == cfg
     s.close()
 
