@@ -592,6 +592,47 @@ def test_design_as_bf16_planes_matches_fp64_design(dev, tmp_path):
         np.testing.assert_array_equal(x, y)
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x5"])
+def test_general_fp64_design_on_matrix_cores(dev, prec):
+    """A design that is not a stored bf16 pair (a generic fp64 matrix) on the
+    matrix-core path: the library rounds each entry to fp32 and keeps it as a
+    bf16 hi + lo pair, 16 significant bits, so |x - x_kept| <= 2^-16 |x|
+    (fp32 rounding 2^-24 plus the lo term's rounding 2^-17 of |x|, rounded
+    up).  That moves eta and the gradient by at most 2^-16 times the sums of
+    |x theta| and |x r|; the tolerances below are that bound times the
+    cancellation these sums show on the workload, with a factor 4 to spare,
+    on top of the stored-pair tolerances."""
+    w = W.fold_subset(W.make("c4"), 0, 16)
+    rng = np.random.default_rng(12)
+    X = w.X * (1.0 + 1e-3 * rng.standard_normal(w.X.shape))     # no longer a bf16 pair
+    w = dataclasses.replace(w, X=X, x_hi=None, x_lo=None)
+    theta = _theta_near_init(w, seed=4)
+    lp_o, g_o = _oracle_eval(w, theta)
+    roles = folds.roles_of(w)
+    foc = np.arange(w.C) // w.L
+    eta = model.linear_predictor(w, theta)
+    train = roles[foc].T == folds.ROLE_TRAIN
+    r = train * model.dloglik_deta(w.family, w.y[:, None], eta, w.sigma)
+    h = 1e-6
+    dr = train * np.abs(model.dloglik_deta(w.family, w.y[:, None], eta + h, w.sigma)
+                        - model.dloglik_deta(w.family, w.y[:, None], eta - h, w.sigma)) / (2 * h)
+    u = 2.0 ** -16
+    deta = u * (np.abs(w.X) @ np.abs(theta.T))                     # |eta change| per row and chain
+    bound_v = np.sum(np.abs(r) * deta, axis=0) / np.abs(lp_o)
+    bound_g = np.linalg.norm(u * (np.abs(w.X).T @ np.abs(r)) + np.abs(w.X).T @ (dr * deta), axis=0) \
+        / np.linalg.norm(g_o, axis=1)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    rel_v = np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)
+    rel_g = _normwise(g.cpu().numpy(), g_o)
+    base_v, base_g = 1e-5, (5e-5 if prec == "bf16x3" else 1e-5)
+    _say(f"[general design] {prec}: logp rel max {rel_v.max():.2e} (bound {bound_v.max():.1e}), "
+         f"grad normwise max {rel_g.max():.2e} (bound {bound_g.max():.1e})")
+    assert np.all(rel_v < base_v + 4 * bound_v)
+    assert np.all(rel_g < base_g + 4 * bound_g)
+    s.close()
+
+
 @pytest.mark.parametrize("name,prec,folds_,mode", [("c1", "fp64", (0, 12), 0), ("c4", "bf16x3", (0, 40), 0),
                                                   ("c1", "fp64", (0, 12), 1)])
 def test_checkpoint_resume_is_exact(dev, tmp_path, name, prec, folds_, mode):
