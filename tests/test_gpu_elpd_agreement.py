@@ -31,7 +31,8 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 CASES = [("c2", "elpd_c2_folds0-50.json", W.PREC_FP32),
-         ("c4", "elpd_c4_folds0-25.json", W.PREC_BF16X3)]
+         ("c4", "elpd_c4_folds0-25.json", W.PREC_BF16X3),
+         ("c5", "elpd_c5_folds0-20.json", W.PREC_BF16X3)]
 
 
 def _say(msg):
