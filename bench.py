@@ -14,7 +14,9 @@ Also reported on the same JSON line:
   roofline      the gradient kernel's algorithmic flops per launch (4 n p C)
                 over its mean launch time from HIP events on the library's
                 stream during the timed region, against the dense bf16 peak;
-                HBM traffic from committed rocprofv3 counter summaries if any
+                HBM traffic from committed rocprofv3 counter summaries if any;
+                on matrix-core workloads also the sustained rate of the same
+                bf16 MFMA on random and on constant operands (mfma_ceiling)
   cpu_baseline  the fp64 CPU oracle on a bounded sample of the same workload
   parity_vs_oracle  the device's log density and gradient against the oracle
                 at the starting positions of that sample's chains
@@ -22,7 +24,7 @@ Also reported on the same JSON line:
                 the same workload, a few steps, and the speedup over it
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5]
        [--precision bf16x3|bf16x5|fp64|fp32|fp64u] [--no-cpu-baseline]
-       [--no-plain-fp64] [--no-time-to-rhat] [--no-autotune]
+       [--no-plain-fp64] [--no-time-to-rhat] [--no-autotune] [--no-mfma-ceiling]
 """
 from __future__ import annotations
 
@@ -124,10 +126,20 @@ def cpu_baseline(w, budget_s=20.0):
                       f"{dt:.1f} s; fp64 numpy oracle, BLAS on {threads or os.cpu_count()} threads"}
 
 
-def traffic_from_profiles(w, prec, kernel_name):
+def current_config(s):
+    """The context's launch shape, or None on the plain fp64 path (which has none)."""
+    from paper_2310_07002_amd import binding
+    try:
+        return s.launch_config()
+    except binding.PcvError:
+        return None
+
+
+def traffic_from_profiles(w, prec, kernel_name, config):
     """HBM bytes per launch of the gradient kernel from the committed counter
-    summary, or None if there is none or the kernel's sources (its .hip file
-    and the shared device header) changed since the counters were taken."""
+    summary, or None if there is none, if it was taken at another launch
+    shape than `config`, or if the kernel's sources (its .hip file and the
+    shared device header) changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{w.name}_{prec}.json")
     csrc = os.path.join(ROOT, "paper_2310_07002_amd", "csrc")
@@ -143,6 +155,8 @@ def traffic_from_profiles(w, prec, kernel_name):
             with open(x, "rb") as f:
                 hh.update(f.read())
         h = hh.hexdigest()[:16]
+        if t.get("launch_config") != config:
+            return None
         return t.get("bytes_per_launch") if t.get("kernel_source_sha256_16") == h else None
     except Exception:
         return None
@@ -165,6 +179,8 @@ def main():
     ap.add_argument("--launch-config", type=int, default=None,
                     help="apply this launch shape (pcv_autotune's encoding) instead of tuning, "
                          "e.g. to profile the shape a full run chose")
+    ap.add_argument("--no-mfma-ceiling", action="store_true",
+                    help="skip timing the bf16 MFMA calibration kernel (matrix-core workloads)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 512 MiB device-to-device copy first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -248,13 +264,25 @@ def main():
     roofline = {"bound": "mfma" if prec.startswith("bf16") else "alu",
                 "kernel": k_name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": (achieved / peak) if achieved else None,
-                "traffic": traffic_from_profiles(w, prec, k_name),
+                "traffic": traffic_from_profiles(w, prec, k_name, current_config(s)),
                 "alg_flops_per_launch": flops_per_launch, "mean_launch_ms": avg_s * 1e3,
                 "launches": k_n}
     if prec.startswith("bf16"):
         # issued bf16 products per algorithmic product: (forward terms + 3 adjoint terms) / 2
         ratio = (3 + 3) / 2 if prec == "bf16x3" else (5 + 3) / 2
         roofline["issued_mfma_frac"] = achieved * ratio / peak if achieved else None
+        if not args.no_mfma_ceiling:
+            # the sustained rate of the same bf16 MFMA on random and on
+            # constant operands (the part lowers its clock to hold its power
+            # limit, more so the more the operand bits switch)
+            rnd = binding.pcv_calib_mfma(1, 40)
+            cst = binding.pcv_calib_mfma(0, 40)
+            roofline["mfma_ceiling"] = {
+                "kernel": "k_calib_mfma (v_mfma_f32_32x32x16_bf16, 2 waves per SIMD, operands from LDS)",
+                "random_bf16_tflops": rnd, "constant_operands_tflops": cst,
+                "issued_frac_of_random_ceiling": achieved * ratio / rnd if achieved else None}
+            log(f"bench: bf16 MFMA ceiling {rnd:.0f} TFLOP/s on random operands, {cst:.0f} on constant ones; "
+                f"the gradient kernel issues {achieved * ratio:.0f}")
 
     acc_check = s.diagnostics()
     assert acc_check["n_draws"] == 2 * args.steps, "timed transitions must be post-warm-up"

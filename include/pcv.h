@@ -459,6 +459,22 @@ pcv_status pcv_timing_enable(pcv_ctx ctx, int32_t on);
 pcv_status pcv_timing_read(pcv_ctx ctx, double* ms_sum, int64_t* n_launches,
                            const char** kernel_name, int32_t reset);
 
+/* Roofline calibration of the bf16 matrix cores (measurement support, no
+ * part of the method).  Times a kernel that keeps every SIMD's matrix core
+ * busy with v_mfma_f32_32x32x16_bf16 products, two waves per SIMD, operands
+ * read from LDS: data_kind 0 multiplies constant operands (every element
+ * 1.0), data_kind 1 seeded random bf16 operands (random sign and mantissa,
+ * magnitudes in [2^-8, 1)), like the split hi and lo planes the gradient
+ * kernel multiplies.  The part lowers its clock to hold its power limit, and
+ * the power of a product grows with the switching activity of its operands,
+ * so the two sustained rates bracket what a bf16 MFMA kernel reaches on this
+ * device.  tflops receives the dense rate (2*32*32*16 flops per product) over
+ * `launches` timed launches after one untimed one, on the null stream of the
+ * current device.  Allocates and frees a small buffer; synchronises.
+ * Errors: PCV_ERR_INVALID_ARG (data_kind not 0 or 1, launches < 1, tflops
+ * NULL), PCV_ERR_NOMEM, PCV_ERR_DEVICE. */
+pcv_status pcv_calib_mfma(int32_t data_kind, int32_t launches, double* tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,8 @@ EXPORTED = ["pcv_init", "pcv_set_stream", "pcv_step", "pcv_diagnostics", "pcv_el
             "pcv_logdensity_grad", "pcv_leapfrog", "pcv_get_state", "pcv_set_state",
             "pcv_get_accumulators", "pcv_autotune", "pcv_save", "pcv_load", "pcv_philox",
             "pcv_adapt", "pcv_init_positions", "pcv_elpd_model", "pcv_compare_models",
-            "pcv_timing_enable", "pcv_timing_read", "pcv_set_launch_config", "pcv_get_launch_config"]
+            "pcv_timing_enable", "pcv_timing_read", "pcv_set_launch_config", "pcv_get_launch_config",
+            "pcv_calib_mfma"]
 
 
 class PcvError(RuntimeError):
@@ -137,6 +138,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
         "pcv_init_positions": ([dp, I64, I64, I64, U64, I64, dp], I32),
         "pcv_timing_enable": ([P, I32], I32),
         "pcv_timing_read": ([P, dp, ctypes.POINTER(I64), ctypes.POINTER(ctypes.c_char_p), I32], I32),
+        "pcv_calib_mfma": ([I32, I32, dp], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -180,6 +182,16 @@ def pcv_philox(seed: int, c0: int, c1: int, c2: int, c3: int, n: int) -> np.ndar
     if st != PCV_OK:
         raise PcvError(st, "pcv_philox failed")
     return out.reshape(n, 4)
+
+
+def pcv_calib_mfma(data_kind: int, launches: int = 50) -> float:
+    """Sustained bf16 32x32x16 MFMA rate in TFLOP/s on constant (0) or random (1) operands."""
+    lib = load_library()
+    out = ctypes.c_double(0.0)
+    st = lib.pcv_calib_mfma(int(data_kind), int(launches), ctypes.byref(out))
+    if st != PCV_OK:
+        raise PcvError(st, "pcv_calib_mfma failed")
+    return out.value
 
 
 class PCV:

@@ -23,7 +23,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 _VALU_INST = [("k_valu.hip", [f"-DPCV_VALU_T={t}", f"-DPCV_VALU_FAM={fam}"], f"k_valu_{t}_{fam}.o")
               for t in ("double", "float") for fam in range(5)]
 SOURCES = [("api.hip", [], "api.o"), ("k_common.hip", [], "k_common.o"), ("k_valu.hip", [], "k_valu.o"),
-           ("k_mfma.hip", [], "k_mfma.o"), ("posthoc.hip", [], "posthoc.o")] + _VALU_INST
+           ("k_mfma.hip", [], "k_mfma.o"), ("posthoc.hip", [], "posthoc.o"),
+           ("calib.hip", [], "calib.o")] + _VALU_INST
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed fp32 instructions in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -129,3 +129,13 @@ def test_interval_folds_need_one_non_train_range():
     assert _expect_invalid(w, intervals=iv) == 1
     iv[k] = (lo, hi, max(0, lo - 9), lo - 4)
     assert _expect_invalid(w, intervals=iv) == 1
+
+
+def test_mfma_calibration_rejects_bad_arguments():
+    """Argument checks come before any device call."""
+    lib = binding.load_library()
+    import ctypes
+    out = ctypes.c_double(0.0)
+    assert lib.pcv_calib_mfma(2, 10, ctypes.byref(out)) == 1
+    assert lib.pcv_calib_mfma(1, 0, ctypes.byref(out)) == 1
+    assert lib.pcv_calib_mfma(0, 10, None) == 1
