@@ -95,35 +95,47 @@ def oracle_parity(w, theta, lp_dev, g_dev):
             "grad_normwise_rel_median": float(np.median(rel_g))}
 
 
-def cpu_baseline(w, budget_s=20.0):
-    """The oracle as it stands (numpy, fp64), on a bounded sample: the first
-    folds of the same workload (same chains, same random streams), from the
-    chains' starts, as many transitions as fit in the time budget."""
-    from oracle import sampler
+def cpu_baseline(w, budget_s=15.0, numpy_budget_s=8.0):
+    """The oracle as it stands, on a bounded sample: the first folds of the
+    same workload (same chains, same random streams), from the chains'
+    starts, as many transitions as fit in the time budget.  The value is the
+    plain C oracle (fp64 loops, chains spread over the host's threads with
+    OpenMP); the numpy oracle (BLAS for the contractions) is timed beside it
+    on the same sample."""
+    from oracle import c_oracle, sampler
     from paper_2310_07002_amd import workloads as W
-    threads = None
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max((i.get("num_threads") or 0) for i in threadpool_info()) or None
-    except Exception:
-        pass
+    host = os.cpu_count() or 1
+    threads = max(1, min(host, int(os.environ.get("OMP_NUM_THREADS") or host)))
     k_sub = baseline_folds(w)
     sub = W.fold_subset(w, 0, k_sub)
-    run = sampler.start(sub)
-    t0 = time.perf_counter()
-    iters = 0
-    while True:
-        sampler.advance(sub, run, 1)
-        iters += 1
-        if time.perf_counter() - t0 > budget_s or iters >= 500:
-            break
-    dt = time.perf_counter() - t0
-    rate = sub.C * sub.n_leapfrog * iters / dt
-    return {"value": rate, "unit": "gradient evals/s", "cores": threads or os.cpu_count(),
-            "kind": "oracle", "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+
+    def timed(step, budget):
+        t0 = time.perf_counter()
+        iters = 0
+        while True:
+            step()
+            iters += 1
+            if time.perf_counter() - t0 > budget or iters >= 500:
+                return iters, time.perf_counter() - t0
+
+    run_c = c_oracle.Run(sub, threads)
+    it_c, dt_c = timed(lambda: run_c.advance(1), budget_s)
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((i.get("num_threads") or 0) for i in threadpool_info()) or None
+    except Exception:
+        pass
+    run_np = sampler.start(sub)
+    it_np, dt_np = timed(lambda: sampler.advance(sub, run_np, 1), numpy_budget_s)
+    per_iter = sub.C * sub.n_leapfrog
+    return {"value": per_iter * it_c / dt_c, "unit": "gradient evals/s", "cores": threads,
+            "kind": "oracle", "cpu": cpu_model(), "host_cpus": host,
             "sample": f"first {k_sub} folds x {sub.L} chains ({sub.C} chains) of the same workload, "
-                      f"{iters} transitions of {sub.n_leapfrog} leapfrog steps from the chains' starts, "
-                      f"{dt:.1f} s; fp64 numpy oracle, BLAS on {threads or os.cpu_count()} threads"}
+                      f"{it_c} transitions of {sub.n_leapfrog} leapfrog steps from the chains' starts, "
+                      f"{dt_c:.1f} s; plain C fp64 oracle (oracle/c), chains over {threads} OpenMP threads",
+            "numpy_oracle": {"value": per_iter * it_np / dt_np, "transitions": it_np, "seconds": dt_np,
+                             "blas_threads": blas}}
 
 
 def current_config(s):

@@ -16,6 +16,9 @@ Modules
   sampler      online single-model LogS sampler                (Algorithm A2)
   diagnostics  elpd, MCSE, ESS, Rhat, Rhat_max                  (Sections 2.4, 4; App. A)
   closed_form  conjugate Gaussian posteriors and predictives (pins for the above)
+  c_oracle     ctypes wrapper of c/pcv_oracle.c: the hot path (masked log density,
+               HMC, Algorithm A2's accumulators, diagnostics) restated in plain C
+               fp64 loops, independently of the numpy modules above
 
 Parity status of every function is stated in its module header.
 """
