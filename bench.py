@@ -149,9 +149,9 @@ def current_config(s):
 
 def traffic_from_profiles(w, prec, kernel_name, config):
     """HBM bytes per launch of the gradient kernel from the committed counter
-    summary, or None if there is none, if it was taken at another launch
-    shape than `config`, or if the kernel's sources (its .hip file and the
-    shared device header) changed since the counters were taken."""
+    summary, or None if there is none, if it holds no counters for launch
+    shape `config`, or if the kernel's sources (its .hip file and the shared
+    device header) changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{w.name}_{prec}.json")
     csrc = os.path.join(ROOT, "paper_2310_07002_amd", "csrc")
@@ -167,9 +167,11 @@ def traffic_from_profiles(w, prec, kernel_name, config):
             with open(x, "rb") as f:
                 hh.update(f.read())
         h = hh.hexdigest()[:16]
-        if t.get("launch_config") != config:
+        if t.get("kernel_source_sha256_16") != h:
             return None
-        return t.get("bytes_per_launch") if t.get("kernel_source_sha256_16") == h else None
+        if t.get("launch_config") == config:
+            return t.get("bytes_per_launch")
+        return t.get("other_launch_configs", {}).get(str(config), {}).get("bytes_per_launch")
     except Exception:
         return None
 
