@@ -26,16 +26,36 @@ def dev():
     return torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("name", ["c1", "c3"])
+def _check_states(th, q, tol, name):
+    """c1, c3: elementwise.  c2, c4: per chain, normwise, 10 x tol -- their
+    step sizes already differ by up to tol, and a trajectory moves each
+    chain by O(|q|), so positions inherit about that relative error, with
+    coordinates near zero (small group effects) far off elementwise."""
+    if name in ("c2", "c4"):
+        rel = np.linalg.norm(th - q, axis=1) / np.linalg.norm(q, axis=1)
+        _say(f"[adapt] {name}: states normwise max {rel.max():.2e}")
+        assert rel.max() < 10 * tol
+    else:
+        np.testing.assert_allclose(th, q, rtol=tol, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["c1", "c3", "c2", "c4"])
 def test_adapt_replays_the_oracle_over_a_short_horizon(dev, name):
-    """c1: fused VALU path; c3 (4996 rows, 8 chains): row-split path.
+    """c1: fused VALU path; c3 (4996 rows, 8 chains), c2 (hierarchical
+    logistic, 62 coordinates) and c4 (Poisson, p = 64): row-split path.
+    The early dual-averaging steps of c2 and c4 overshoot into divergent
+    trajectories (non-finite energies), which both sides reject alike.
     16 transitions: buffers of 2 and 1 around one slow window of 13, so the
     schedule, the dual averaging, the window variance and the restart all
     run.  The horizon is short on purpose: in the early phase the dual
     averaging's feedback (step size -> acceptance -> step size) multiplies a
     rounding difference by about two per transition, so two correct
     implementations that add in different orders drift apart after a few
-    dozen transitions (the long runs are checked statistically below)."""
+    dozen transitions (the long runs are checked statistically below).
+    The rounding that feeds it is that of the energy difference, about
+    eps_mach * |log pi|: the c2 and c4 log densities are 10-100 times larger
+    in magnitude than c1's, so their replays are held to 1e-6, not 1e-7."""
+    tol = 1e-6 if name in ("c2", "c4") else 1e-7
     n_adapt = 16
     f = W.full_data(W.make(name), L=8, n_warmup=n_adapt + 10)
     _say(f"[adapt] {name} n_adapt={n_adapt}")
@@ -45,9 +65,9 @@ def test_adapt_replays_the_oracle_over_a_short_horizon(dev, name):
     fa, st, eps, acc = adapt.adapt(f, n_adapt, 0.8)
     _say(f"[adapt] {name}: eps {r['step_size']:.9g} (oracle {fa.step_size:.9g})")
     assert adapt.slow_window_ends(n_adapt) == [15]
-    assert r["step_size"] == pytest.approx(fa.step_size, rel=1e-7)
-    np.testing.assert_allclose(r["inv_mass"], fa.inv_mass, rtol=1e-7)
-    np.testing.assert_allclose(th, st.q, rtol=1e-7, atol=1e-12)
+    assert r["step_size"] == pytest.approx(fa.step_size, rel=tol)
+    np.testing.assert_allclose(r["inv_mass"], fa.inv_mass, rtol=tol)
+    _check_states(th, st.q, tol, name)
     # the context keeps the adapted tuning: further transitions still replay
     s.step(3)
     th2, _, _ = s.get_state()
@@ -55,7 +75,7 @@ def test_adapt_replays_the_oracle_over_a_short_horizon(dev, name):
     roles = folds.roles_of(fa)
     for t in range(n_adapt, n_adapt + 3):
         st, _, _ = hmc.transition(fa, st, t, roles, np.zeros(fa.C, dtype=np.int64), np.arange(fa.C))
-    np.testing.assert_allclose(th2, st.q, rtol=1e-7, atol=1e-12)
+    _check_states(th2, st.q, tol, name)
     s.close()
 
 
@@ -116,17 +136,25 @@ def test_workflow_full_data_tuning_then_cv(dev):
 
 
 def test_adapt_on_the_matrix_core_path(dev):
-    """Full-data adaptation of the Poisson GLM (p=64) on the bf16x3 path:
-    the schedule runs through the eager transitions of that path and leaves
-    a finite, positive tuning; the context then steps with it (captured
-    transition graphs)."""
+    """Full-data adaptation of the Poisson GLM (p=64) on the bf16x3 path over
+    600 transitions, against the fp64 oracle's own 600-transition
+    adaptation: the two runs part ways after a few transitions (bf16 split
+    rounding), so they are compared as estimates of the same tuning -- the
+    step size within 25% and every inverse-mass entry (a windowed posterior
+    variance of 8 chains) within 30%.  The context then steps with it
+    (captured transition graphs)."""
     w = W.make("c4")
-    f = W.full_data(w, L=8, n_warmup=200)
+    f = W.full_data(w, L=8, n_warmup=1200)
     s = binding.PCV.from_workload(f, precision=W.PREC_BF16X3)
-    r = s.adapt(120, 0.8)
-    _say(f"[adapt] c4 bf16x3: eps {r['step_size']:.4f}, Minv range {r['inv_mass'].min():.3g}..{r['inv_mass'].max():.3g}")
+    r = s.adapt(600, 0.8)
+    fa, _, _, _ = adapt.adapt(f, 600, 0.8)
+    ratio = r["inv_mass"] / fa.inv_mass
+    _say(f"[adapt] c4 bf16x3: eps {r['step_size']:.4f} (oracle {fa.step_size:.4f}), "
+         f"Minv / oracle's in {ratio.min():.3f}..{ratio.max():.3f}")
     assert np.isfinite(r["step_size"]) and r["step_size"] > 0
     assert np.isfinite(r["inv_mass"]).all() and (r["inv_mass"] > 0).all()
+    assert abs(r["step_size"] / fa.step_size - 1.0) < 0.25
+    assert (np.abs(ratio - 1.0) < 0.3).all()
     s.step(10)
     th, lp, _ = s.get_state()
     assert np.isfinite(th).all() and np.isfinite(lp).all()
