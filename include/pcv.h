@@ -64,7 +64,8 @@ enum {
   PCV_PREC_FP64 = 0,          /* fp64 VALU kernels (p <= 64)                        */
   PCV_PREC_FP32 = 1,          /* fp32 VALU kernels (p <= 64)                        */
   PCV_PREC_BF16X3 = 2,        /* bf16 MFMA, X and theta split hi+lo, 3 products each
-                                 way, fp32 accumulation (p = 64 or 128)             */
+                                 way, fp32 accumulation (p <= 128; the kernels run
+                                 at width 64 or 128 with zero columns past p)       */
   PCV_PREC_BF16X5 = 3,        /* as BF16X3 with a three-term theta split in the
                                  forward product (5 products), fp32-exact eta        */
   PCV_PREC_FP64_UNFUSED = 4   /* plain fp64 path: library DGEMMs with eta and the

@@ -26,10 +26,11 @@ int valu_pb(int64_t p, bool fp64);
 hipError_t launch_mfma(const DevModel& m, int shape, const uint4* Xpk, const float* ty, const int32_t* tfid,
                        const uint32_t* tflag, float* Gpart, double* Vpart, int n_tiles, int tiles_per_split,
                        int n_splits, int fwd, bool value, hipStream_t st);
-hipError_t launch_mfma_pack(const double* X, int64_t n, int P, int n_tiles, int shape, uint4* out, hipStream_t st);
+hipError_t launch_mfma_pack(const double* X, int64_t n, int p, int n_tiles, int shape, uint4* out, hipStream_t st);
 int mfma_chain_tile();
 int mfma_rows_per_tile();
-int mfma_nfrag(int P, int shape);
+int mfma_nfrag(int p, int shape);
+int mfma_width(int64_t p);
 hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st);
 hipError_t launch_reduce_f32(const DevModel& m, const float* G, int ns, int mode, hipStream_t st);
 hipError_t launch_reduce_f64(const DevModel& m, const double* G, int ns, int mode, hipStream_t st);
@@ -487,11 +488,11 @@ pcv_status apply_mfma_shape(pcv_ctx ctx, int shape) {
     return fail(ctx, PCV_ERR_INVALID_ARG, "unknown MFMA shape");
   const int layout = shape == MFMA_SHAPE_16X16X32 ? 0 : 1;   // both 32x32x16 kernels share a packing
   if (!ctx->Xpk_shape[layout]) {
-    const int P = static_cast<int>(ctx->m.p);
-    const size_t nfr = static_cast<size_t>(ctx->n_tiles) * mfma_nfrag(P, shape) * 64;
+    const int p = static_cast<int>(ctx->m.p);
+    const size_t nfr = static_cast<size_t>(ctx->n_tiles) * mfma_nfrag(p, shape) * 64;
     uint4* xp;
     TRY(dalloc(ctx, &xp, nfr));
-    CK(launch_mfma_pack(ctx->m.X64, ctx->m.n, P, ctx->n_tiles, shape, xp, ctx->st));
+    CK(launch_mfma_pack(ctx->m.X64, ctx->m.n, p, ctx->n_tiles, shape, xp, ctx->st));
     ctx->Xpk_shape[layout] = xp;
   }
   ctx->Xpk = ctx->Xpk_shape[layout];
@@ -673,7 +674,7 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     ctx->path = PATH_MFMA;
     ctx->fwd = md->precision == PCV_PREC_BF16X5 ? 5 : 3;
     if (hier) return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path supports the GLM families");
-    if (p != 64 && p != 128) return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path supports p = 64 or 128");
+    if (p > 128) return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path supports p <= 128");
     if (fm->kind == PCV_FOLDS_DENSE)
       return fail(ctx, PCV_ERR_UNSUPPORTED, "bf16 MFMA path takes index or interval fold encodings");
   } else {

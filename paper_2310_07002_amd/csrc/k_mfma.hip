@@ -31,6 +31,11 @@ constexpr int MF_CHAINS_PER_WAVE = 32;
 constexpr int MF_CHAIN_TILE = MF_WAVES * MF_CHAINS_PER_WAVE;  // 256
 constexpr int MF_ROWS = 32;                                   // rows per tile
 
+// The kernels' design width P: p rounded up to 64 or 128.  X is packed with
+// zero columns past p, theta is taken as zero there, and only the first p
+// gradient rows are written, so any 1 <= p <= 128 runs on the P kernels.
+int mfma_width(int64_t p) { return p <= 64 ? 64 : 128; }
+
 // fragments per 32-row tile: forward 2 (M) x P/32 (K) x 2 planes, adjoint P/16 (M) x 2 planes
 __host__ __device__ constexpr int mf_nfrag_fwd(int P) { return 2 * (P / 32) * 2; }
 __host__ __device__ constexpr int mf_nfrag(int P) { return mf_nfrag_fwd(P) + (P / 16) * 2; }
@@ -160,14 +165,13 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
     const uint8_t* mrow = cv ? mask_row(m, c) : nullptr;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      // mask bytes of this lane's 8 covariates in one load (p is a multiple
-      // of 32 here, so the slice is 8-byte aligned); all used without masks
-      const uint64_t mbits = mrow ? *reinterpret_cast<const uint64_t*>(mrow + kb * 32 + 8 * g4) : ~0ull;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
+        // coordinates past p (the design's zero columns up to the kernel's
+        // width P) and coordinates a nested model drops take theta = 0
         const int j = kb * 32 + 8 * g4 + e;
-        const double t = cv && ((mbits >> (8 * e)) & 0xffu)
-                             ? m.q1[static_cast<int64_t>(j) * m.C + c] * mf_theta_scale<FAM>() : 0.0;
+        const bool used = cv && j < m.p && (!mrow || mrow[j]);
+        const double t = used ? m.q1[static_cast<int64_t>(j) * m.C + c] * mf_theta_scale<FAM>() : 0.0;
         if (NT == 2) {
           const float t32 = static_cast<float>(t);
           const __bf16 h = to_bf16(t32);
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
 #pragma unroll
         for (int ii = 0; ii < 4; ++ii) {
           const int j = mb * 16 + 4 * g4 + ii;
-          a.Gpart[(static_cast<int64_t>(sp) * P + j) * m.C + c] = gacc[mb][cb][ii];
+          if (j < m.p) a.Gpart[(static_cast<int64_t>(sp) * m.p + j) * m.C + c] = gacc[mb][cb][ii];
         }
     }
     if (VALUE) {
@@ -535,12 +539,11 @@ __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
     const uint8_t* mrow = cvalid ? mask_row(m, cidx) : nullptr;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      const uint64_t mbits = mrow ? *reinterpret_cast<const uint64_t*>(mrow + kb * 16 + 8 * hh) : ~0ull;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int j = kb * 16 + 8 * hh + e;
-        const double t = cvalid && ((mbits >> (8 * e)) & 0xffu)
-                             ? m.q1[static_cast<int64_t>(j) * m.C + cidx] * mf_theta_scale<FAM>() : 0.0;
+        const bool used = cvalid && j < m.p && (!mrow || mrow[j]);
+        const double t = used ? m.q1[static_cast<int64_t>(j) * m.C + cidx] * mf_theta_scale<FAM>() : 0.0;
         if (NT == 2) {
           const float t32 = static_cast<float>(t);
           const __bf16 h = to_bf16(t32);
@@ -773,7 +776,7 @@ __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int j = mb * 32 + m2_row(q, hh);
-        a.Gpart[(static_cast<int64_t>(sp) * P + j) * m.C + cidx] = gacc[mb][q];
+        if (j < m.p) a.Gpart[(static_cast<int64_t>(sp) * m.p + j) * m.C + cidx] = gacc[mb][q];
       }
   }
   if (VALUE) {
@@ -783,11 +786,13 @@ __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
   }
 }
 
-// Pack X (fp64, row-major) for k_mfma32, split hi/lo: forward fragment
+// Pack X (fp64, row-major, p columns) for k_mfma32 at width P >= p (zero
+// columns past p), split hi/lo: forward fragment
 // (kb, plane) lane l holds row l%32, columns 16 kb + 8 (l/32) + e; adjoint
 // fragment (mb, kh, plane) lane l holds column 32 mb + l%32 at the rows of
 // K half kh in accumulator order (m2_row).
-__global__ void k_mfma32_pack(const double* __restrict__ X, int64_t n, int P, int n_tiles, uint4* __restrict__ out) {
+__global__ void k_mfma32_pack(const double* __restrict__ X, int64_t n, int p, int P, int n_tiles,
+                              uint4* __restrict__ out) {
   const int nf = m2_nfrag(P), nff = m2_nfrag_fwd(P);
   const int64_t total = static_cast<int64_t>(n_tiles) * nf * 64;
   for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
@@ -804,7 +809,7 @@ __global__ void k_mfma32_pack(const double* __restrict__ X, int64_t n, int P, in
       const int64_t row = row0 + l32;
       for (int e = 0; e < 8; ++e) {
         const int col = kb * 16 + 8 * h + e;
-        const float x = row < n ? static_cast<float>(X[row * P + col]) : 0.f;
+        const float x = row < n && col < p ? static_cast<float>(X[row * p + col]) : 0.f;
         const __bf16 hb = to_bf16(x);
         v[e] = plane == 0 ? hb : to_bf16(x - static_cast<float>(hb));
       }
@@ -814,7 +819,7 @@ __global__ void k_mfma32_pack(const double* __restrict__ X, int64_t n, int P, in
       const int col = mb * 32 + l32;
       for (int e = 0; e < 8; ++e) {
         const int64_t row = row0 + 16 * kh + m2_row(e, h);
-        const float x = row < n ? static_cast<float>(X[row * P + col]) : 0.f;
+        const float x = row < n && col < p ? static_cast<float>(X[row * p + col]) : 0.f;
         const __bf16 hb = to_bf16(x);
         v[e] = plane == 0 ? hb : to_bf16(x - static_cast<float>(hb));
       }
@@ -823,8 +828,10 @@ __global__ void k_mfma32_pack(const double* __restrict__ X, int64_t n, int P, in
   }
 }
 
-// Pack X (fp64, row-major) into the two fragment orders, split hi/lo.
-__global__ void k_mfma_pack(const double* __restrict__ X, int64_t n, int P, int n_tiles, uint4* __restrict__ out) {
+// Pack X (fp64, row-major, p columns) into the two fragment orders at width
+// P >= p (zero columns past p), split hi/lo.
+__global__ void k_mfma_pack(const double* __restrict__ X, int64_t n, int p, int P, int n_tiles,
+                            uint4* __restrict__ out) {
   const int nf = mf_nfrag(P), nff = mf_nfrag_fwd(P), KB = P / 32;
   const int64_t total = static_cast<int64_t>(n_tiles) * nf * 64;
   for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
@@ -842,7 +849,7 @@ __global__ void k_mfma_pack(const double* __restrict__ X, int64_t n, int P, int 
       const int64_t row = row0 + mh * 16 + l16;
       for (int e = 0; e < 8; ++e) {
         const int col = kb * 32 + 8 * g4 + e;
-        const float x = row < n ? static_cast<float>(X[row * P + col]) : 0.f;
+        const float x = row < n && col < p ? static_cast<float>(X[row * p + col]) : 0.f;
         const __bf16 h = to_bf16(x);
         v[e] = plane == 0 ? h : to_bf16(x - static_cast<float>(h));
       }
@@ -853,7 +860,7 @@ __global__ void k_mfma_pack(const double* __restrict__ X, int64_t n, int P, int 
       const int col = mb * 16 + l16;
       for (int e = 0; e < 8; ++e) {
         const int64_t row = row0 + (e < 4 ? 4 * g4 + e : 16 + 4 * g4 + (e - 4));
-        const float x = row < n ? static_cast<float>(X[row * P + col]) : 0.f;
+        const float x = row < n && col < p ? static_cast<float>(X[row * p + col]) : 0.f;
         const __bf16 h = to_bf16(x);
         v[e] = plane == 0 ? h : to_bf16(x - static_cast<float>(h));
       }
@@ -917,21 +924,26 @@ hipError_t launch_mfma(const DevModel& m, int shape, const uint4* Xpk, const flo
   a.n_splits = n_splits;
   const int n_ct = static_cast<int>((m.C + MF_CHAIN_TILE - 1) / MF_CHAIN_TILE);
   const int nblk = n_ct * n_splits;
-  const int P = static_cast<int>(m.p);
+  const int P = mfma_width(m.p);
   if (shape == MFMA_SHAPE_32X32X16) return launch_mfma_s<MFMA_SHAPE_32X32X16>(a, P, fwd, value, nblk, st);
   if (shape == MFMA_SHAPE_32X32X16_IL) return launch_mfma_s<MFMA_SHAPE_32X32X16_IL>(a, P, fwd, value, nblk, st);
   if (shape == MFMA_SHAPE_16X16X32) return launch_mfma_s<MFMA_SHAPE_16X16X32>(a, P, fwd, value, nblk, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_pack(const double* X, int64_t n, int P, int n_tiles, int shape, uint4* out, hipStream_t st) {
-  if (shape != MFMA_SHAPE_16X16X32) hipLaunchKernelGGL(k_mfma32_pack, dim3(1024), dim3(256), 0, st, X, n, P, n_tiles, out);
-  else hipLaunchKernelGGL(k_mfma_pack, dim3(1024), dim3(256), 0, st, X, n, P, n_tiles, out);
+hipError_t launch_mfma_pack(const double* X, int64_t n, int p, int n_tiles, int shape, uint4* out, hipStream_t st) {
+  const int P = mfma_width(p);
+  if (shape != MFMA_SHAPE_16X16X32)
+    hipLaunchKernelGGL(k_mfma32_pack, dim3(1024), dim3(256), 0, st, X, n, p, P, n_tiles, out);
+  else hipLaunchKernelGGL(k_mfma_pack, dim3(1024), dim3(256), 0, st, X, n, p, P, n_tiles, out);
   return hipGetLastError();
 }
 
 int mfma_chain_tile() { return MF_CHAIN_TILE; }
 int mfma_rows_per_tile() { return MF_ROWS; }
-int mfma_nfrag(int P, int shape) { return shape != MFMA_SHAPE_16X16X32 ? m2_nfrag(P) : mf_nfrag(P); }
+int mfma_nfrag(int p, int shape) {
+  const int P = mfma_width(p);
+  return shape != MFMA_SHAPE_16X16X32 ? m2_nfrag(P) : mf_nfrag(P);
+}
 
 }  // namespace pcv

@@ -81,8 +81,14 @@ def test_family_support_is_checked():
 
 
 def test_unsupported_shapes_are_reported():
+    """The matrix-core kernels go up to 128 covariates, the VALU kernels to
+    64: wider designs are refused before any device work."""
     w = W.fold_subset(W.make("c1"), 0, 3)
-    assert _expect_invalid(w, precision=W.PREC_BF16X3) == 5
+    rng = np.random.default_rng(0)
+    wide = dataclasses.replace(w, X=rng.standard_normal((w.n, 130)), prior_scale=np.ones(130),
+                               inv_mass=np.ones(130), init_pos=np.zeros((w.C, 130)), x_hi=None, x_lo=None)
+    assert _expect_invalid(wide, precision=W.PREC_BF16X3) == 5
+    assert _expect_invalid(wide, precision=W.PREC_FP32) == 5
 
 
 def test_model_masks_are_validated():
