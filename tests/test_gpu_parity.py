@@ -166,6 +166,31 @@ def test_mfma_tile_shapes_match_oracle(dev, shape, label, make_w, prec, tol_v, t
     s.close()
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("label,make_w,prec", [(c[0], c[1], c[2]) for c in SHAPE_CASES if c[2] == "bf16x3"])
+def test_leapfrog_every_tile_shape_matches_oracle(dev, shape, label, make_w, prec):
+    """Eight leapfrog steps in every launch shape: seven gradient-only
+    launches (where the masks are applied after the tile's MFMAs, on tiles
+    whose flag marks the wave) and one value launch, against the oracle's
+    trajectory at the 8-step BF16X3 bound."""
+    w = make_w()
+    roles = folds.roles_of(w)
+    foc = np.arange(w.C) // w.L
+    q0 = _theta_near_init(w, seed=11)
+    p0 = philox.momentum_normals(w.seed, w.chain_offset + np.arange(w.C), 0, w.d) / np.sqrt(w.inv_mass)
+    g0 = model.grad_log_density(w, q0, roles, foc)
+    q1, p1, _, lp1 = hmc.leapfrog(w, q0, p0, g0, 8, w.step_size, roles, foc)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    s.set_launch_config(256 * shape + 7)
+    qg, pg, lpg, _ = s.leapfrog(torch.tensor(q0, device=dev), torch.tensor(p0, device=dev), 8)
+    eq = _normwise(qg.cpu().numpy(), q1)
+    ep = _normwise(pg.cpu().numpy(), p1)
+    ev = np.abs(lpg.cpu().numpy() - lp1) / np.abs(lp1)
+    _say(f"[leapfrog shape {shape}] {label}: q {eq.max():.2e}  p {ep.max():.2e}  logp {ev.max():.2e}")
+    assert eq.max() < 2e-5 and ep.max() < 2e-5 and ev.max() < 2e-5
+    s.close()
+
+
 @pytest.mark.parametrize("prec,tol_v,tol_g", [("bf16x3", 1e-5, 5e-5), ("bf16x5", 1e-5, 1e-5)])
 def test_interval_folds_on_matrix_cores(dev, prec, tol_v, tol_g):
     """hv-block style folds (test block plus a buffer of h rows each side,
