@@ -147,6 +147,23 @@ def test_runs_replay_numpy_oracle(name, folds_, n_iter, over):
     assert dc["n_divergent"] == do["n_divergent"] and dc["n_draws"] == ro.acc.n_draws
 
 
+def test_fold_encodings_agree():
+    """The same folds given as an index, as intervals and as a dense role
+    matrix: identical log densities, gradients and log predictives."""
+    w = W.fold_subset(W.make("c3"), 0, 6)                    # hv-block intervals
+    theta = w.init_pos + 0.1 * np.random.default_rng(5).standard_normal(w.init_pos.shape)
+    a = c_oracle.log_density_grad(w, theta)
+    b = c_oracle.log_density_grad(W.with_dense_roles(w), theta)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+    w1 = W.fold_subset(W.make("c1"), 0, 10)                   # LOO index
+    theta1 = w1.init_pos + 0.1 * np.random.default_rng(6).standard_normal(w1.init_pos.shape)
+    a = c_oracle.log_density_grad(w1, theta1)
+    b = c_oracle.log_density_grad(W.with_dense_roles(w1), theta1)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
 def test_divergent_transitions_are_counted_alike():
     """A step size far past the leapfrog's stability limit: every energy
     error exceeds the divergence threshold, none is accepted, and both
