@@ -118,8 +118,13 @@ def cpu_baseline(w, budget_s=15.0, numpy_budget_s=8.0):
             if time.perf_counter() - t0 > budget or iters >= 500:
                 return iters, time.perf_counter() - t0
 
-    run_c = c_oracle.Run(sub, threads)
-    it_c, dt_c = timed(lambda: run_c.advance(1), budget_s)
+    try:
+        run_c = c_oracle.Run(sub, threads)
+    except (OSError, RuntimeError) as e:      # no C compiler or library on this host
+        log(f"bench: C oracle unavailable ({e}); timing the numpy oracle only")
+        run_c = None
+    if run_c is not None:
+        it_c, dt_c = timed(lambda: run_c.advance(1), budget_s)
     blas = None
     try:
         from threadpoolctl import threadpool_info
@@ -127,15 +132,22 @@ def cpu_baseline(w, budget_s=15.0, numpy_budget_s=8.0):
     except Exception:
         pass
     run_np = sampler.start(sub)
-    it_np, dt_np = timed(lambda: sampler.advance(sub, run_np, 1), numpy_budget_s)
+    it_np, dt_np = timed(lambda: sampler.advance(sub, run_np, 1), numpy_budget_s if run_c is not None else budget_s)
     per_iter = sub.C * sub.n_leapfrog
+    numpy_leg = {"value": per_iter * it_np / dt_np, "transitions": it_np, "seconds": dt_np, "blas_threads": blas}
+    if run_c is None:
+        return {"value": numpy_leg["value"], "unit": "gradient evals/s", "cores": blas or host, "kind": "oracle",
+                "cpu": cpu_model(), "host_cpus": host,
+                "sample": f"first {k_sub} folds x {sub.L} chains ({sub.C} chains) of the same workload, "
+                          f"{it_np} transitions of {sub.n_leapfrog} leapfrog steps from the chains' starts, "
+                          f"{dt_np:.1f} s; fp64 numpy oracle, BLAS on {blas or host} threads",
+                "numpy_oracle": numpy_leg}
     return {"value": per_iter * it_c / dt_c, "unit": "gradient evals/s", "cores": threads,
             "kind": "oracle", "cpu": cpu_model(), "host_cpus": host,
             "sample": f"first {k_sub} folds x {sub.L} chains ({sub.C} chains) of the same workload, "
                       f"{it_c} transitions of {sub.n_leapfrog} leapfrog steps from the chains' starts, "
                       f"{dt_c:.1f} s; plain C fp64 oracle (oracle/c), chains over {threads} OpenMP threads",
-            "numpy_oracle": {"value": per_iter * it_np / dt_np, "transitions": it_np, "seconds": dt_np,
-                             "blas_threads": blas}}
+            "numpy_oracle": numpy_leg}
 
 
 def current_config(s):
