@@ -83,6 +83,9 @@ struct pcv_ctx_s {
   rocblas_handle rb = nullptr;
   double* eta = nullptr;
   double* Gpart64 = nullptr;
+  double* theta_cd = nullptr;   // [C][p] copy of theta (chain-major) for the library GEMM
+  int unf_splits = 1;           // row splits of the adjoint GEMM (a batched call; k_reduce adds them)
+  int64_t unf_rows = 0;         // rows per split (the last split may be shorter)
   int64_t chunk = 0;
   // diagnostics
   double* fold_buf = nullptr;
@@ -224,20 +227,40 @@ pcv_status split_partials(pcv_ctx ctx, bool value) {
     timing_end(ctx);
     return PCV_OK;
   }
-  // unfused fp64: eta = X Theta (library GEMM), residual, G' = R' X (library GEMM)
+  // unfused fp64: eta = X Theta (library GEMM), residual, G' = R' X (library GEMM).
+  // In rocBLAS's column-major terms X [n][p] is p x n and a chain-major copy
+  // of theta [C][p] is p x C, so eta (n x chunk, one column per chain) is
+  // X^T theta_chunk; G' (chunk x p, written straight into the [p][C]
+  // partials) is eta^T X^T.  Of the operand layouts measured for these
+  // shapes (small p, long n), these two ran fastest.
   if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
   timing_begin(ctx);
   const double one = 1.0, zero = 0.0;
+  CK(launch_to_cd(m.q1, ctx->theta_cd, m.C, m.p, ctx->st));
   for (int64_t c0 = 0; c0 < m.C; c0 += ctx->chunk) {
     const int64_t cc = std::min<int64_t>(ctx->chunk, m.C - c0);
-    if (rocblas_dgemm(ctx->rb, rocblas_operation_transpose, rocblas_operation_transpose, (rocblas_int)m.n,
-                      (rocblas_int)cc, (rocblas_int)m.p, &one, m.X64, (rocblas_int)m.p, m.q1 + c0,
-                      (rocblas_int)m.C, &zero, ctx->eta, (rocblas_int)m.n) != rocblas_status_success)
+    if (rocblas_dgemm(ctx->rb, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)m.n,
+                      (rocblas_int)cc, (rocblas_int)m.p, &one, m.X64, (rocblas_int)m.p, ctx->theta_cd + c0 * m.p,
+                      (rocblas_int)m.p, &zero, ctx->eta, (rocblas_int)m.n) != rocblas_status_success)
       return fail(ctx, PCV_ERR_DEVICE, "rocblas_dgemm (eta) failed");
     CK(launch_unfused_resid(m, ctx->eta, c0, cc, ctx->Vpart, value ? 1 : 0, ctx->st));
-    if (rocblas_dgemm(ctx->rb, rocblas_operation_transpose, rocblas_operation_transpose, (rocblas_int)cc,
-                      (rocblas_int)m.p, (rocblas_int)m.n, &one, ctx->eta, (rocblas_int)m.n, m.X64,
-                      (rocblas_int)m.p, &zero, ctx->Gpart64 + c0, (rocblas_int)m.C) != rocblas_status_success)
+    // the adjoint's output is only chunk x p, so its rows are split into
+    // independent products of one batched call (enough tiles to fill the
+    // chip); the partials are summed in split order by k_reduce
+    const int64_t rs = ctx->unf_rows;
+    const int64_t full = m.n / rs, rem = m.n - full * rs;
+    if (full > 0 &&
+        rocblas_dgemm_strided_batched(ctx->rb, rocblas_operation_transpose, rocblas_operation_transpose,
+                                      (rocblas_int)cc, (rocblas_int)m.p, (rocblas_int)rs, &one, ctx->eta,
+                                      (rocblas_int)m.n, (rocblas_stride)rs, m.X64, (rocblas_int)m.p,
+                                      (rocblas_stride)(rs * m.p), &zero, ctx->Gpart64 + c0, (rocblas_int)m.C,
+                                      (rocblas_stride)(m.p * m.C), (rocblas_int)full) != rocblas_status_success)
+      return fail(ctx, PCV_ERR_DEVICE, "rocblas_dgemm_strided_batched (gradient) failed");
+    if (rem > 0 &&
+        rocblas_dgemm(ctx->rb, rocblas_operation_transpose, rocblas_operation_transpose, (rocblas_int)cc,
+                      (rocblas_int)m.p, (rocblas_int)rem, &one, ctx->eta + full * rs, (rocblas_int)m.n,
+                      m.X64 + full * rs * m.p, (rocblas_int)m.p, &zero, ctx->Gpart64 + full * m.p * m.C + c0,
+                      (rocblas_int)m.C) != rocblas_status_success)
       return fail(ctx, PCV_ERR_DEVICE, "rocblas_dgemm (gradient) failed");
   }
   timing_end(ctx);
@@ -255,7 +278,7 @@ pcv_status split_reduce(pcv_ctx ctx, int mode) {
     }
   }
   else if (ctx->path == PATH_MFMA) CK(launch_reduce_f32(ctx->m, ctx->Gpart, ctx->n_splits, mode, ctx->st));
-  else CK(launch_reduce_f64(ctx->m, ctx->Gpart64, 1, mode, ctx->st));
+  else CK(launch_reduce_f64(ctx->m, ctx->Gpart64, ctx->unf_splits, mode, ctx->st));
   return PCV_OK;
 }
 
@@ -977,7 +1000,16 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     rocblas_set_stream(ctx->rb, ctx->st);
     ctx->chunk = std::max<int64_t>(1, std::min<int64_t>(C, (int64_t{1} << 28) / n));
     TRY(dalloc(ctx, &ctx->eta, static_cast<size_t>(n) * ctx->chunk));
-    TRY(dalloc(ctx, &ctx->Gpart64, dc));
+    {
+      // adjoint row splits: about 256 output tiles of 128 x 128 per chunk
+      const int64_t tiles = ((ctx->chunk + 127) / 128) * ((p + 127) / 128);
+      const int64_t want = std::max<int64_t>(1, std::min<int64_t>({64, 256 / std::max<int64_t>(1, tiles), n}));
+      ctx->unf_rows = (n + want - 1) / want;
+      const int64_t full = n / ctx->unf_rows;
+      ctx->unf_splits = static_cast<int>(full + (n - full * ctx->unf_rows > 0 ? 1 : 0));
+    }
+    TRY(dalloc(ctx, &ctx->Gpart64, dc * ctx->unf_splits));
+    TRY(dalloc(ctx, &ctx->theta_cd, static_cast<size_t>(C) * p));
   }
 
   // ---- constants, initial state ------------------------------------------
