@@ -248,7 +248,8 @@ def main():
         tune["seconds"] = time.perf_counter() - ta
         kname = s.timing_read(reset=True)[2]
         tune["knob"] = ("waves per workgroup" if "fused" in kname else
-                        "256 x MFMA tile (0: 16x16x32, 1: 32x32x16) + row splits" if "mfma" in kname
+                        ("256 x kernel shape (0: 16x16x32, 1: 32x32x16, 2: 32x32x16 free schedule, "
+                         "3: 16x16x32 with 16 chains per wave) + row splits") if "mfma" in kname
                         else "row splits")
         log(f"bench: autotune chose {tune['knob']} = {tune['config']} ({tune['ms']:.4f} ms) in {tune['seconds']:.2f} s")
     s.step(args.warmup)

@@ -397,9 +397,10 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
 
 /* Autotuner for the hot kernel's launch shape.  It times candidate shapes of
  * the gradient kernel:
- * - matrix-core path: the MFMA tile shape (16x16x32 or 32x32x16 bf16
- *   products) and the number of row splits per 256-chain tile, around the
- *   analytic choice made at init;
+ * - matrix-core path: the kernel shape (16x16x32 or 32x32x16 bf16 MFMA
+ *   tiles, and at design widths up to 64 a 16x16x32 kernel with 16 chains
+ *   per wave whose registers fit two workgroups per CU) and the number of
+ *   row splits per chain tile, around the analytic choice made at init;
  * - fused VALU path: waves per workgroup, each owning a range of rows.
  * Timing runs on a scratch copy of the current positions, so the chains are
  * untouched.  The fastest shape is kept, and the captured transition graph is
@@ -409,9 +410,12 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
  * applied without timing; a miss is timed and written back (created,
  * updated or extended).
  * config receives the shape as one integer (matrix-core path:
- * 256 * tile + splits, tile 0 = 16x16x32 and 1 = 32x32x16 MFMAs; row-split
- * VALU path: splits; fused VALU path: waves); ms receives its mean kernel
- * time (both optional).  Synchronises.
+ * 256 * shape + splits, shape 0 = 16x16x32 MFMAs with 32 chains per wave
+ * (256 per workgroup), 1 = 32x32x16 MFMAs in program order, 2 = the same
+ * scheduled freely by the compiler, 3 = 16x16x32 MFMAs with 16 chains per
+ * wave (128 per workgroup; p <= 64 only); row-split VALU path: splits; fused
+ * VALU path: waves); ms receives its mean kernel time (both optional).
+ * Synchronises.
  * Errors: PCV_ERR_UNSUPPORTED on the plain fp64 path; PCV_ERR_INVALID_ARG if
  * the cache cannot be written; PCV_ERR_DEVICE. */
 pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, double* ms);

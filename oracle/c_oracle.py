@@ -33,7 +33,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the C oracle (IEEE fp64: no fast-math) into LIB."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
+        tmp = f"{LIB}.{os.getpid()}.tmp"    # per process: parallel test workers may build at once
         cmd = [CC, "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:

@@ -27,7 +27,9 @@ hipError_t launch_mfma(const DevModel& m, int shape, const uint4* Xpk, const flo
                        const uint32_t* tflag, float* Gpart, double* Vpart, int n_tiles, int tiles_per_split,
                        int n_splits, int fwd, bool value, hipStream_t st);
 hipError_t launch_mfma_pack(const double* X, int64_t n, int p, int n_tiles, int shape, uint4* out, hipStream_t st);
-int mfma_chain_tile();
+int mfma_chain_tile(int shape);
+int mfma_layout(int shape);
+bool mfma_shape_ok(int shape, int64_t p);
 int mfma_rows_per_tile();
 int mfma_nfrag(int p, int shape);
 int mfma_width(int64_t p);
@@ -507,9 +509,9 @@ namespace {
 // MFMA path: switch the gradient kernel's tile shape, packing X for it on
 // first use (the fp64 design stays resident for that).
 pcv_status apply_mfma_shape(pcv_ctx ctx, int shape) {
-  if (shape < MFMA_SHAPE_16X16X32 || shape > MFMA_SHAPE_32X32X16_IL)
-    return fail(ctx, PCV_ERR_INVALID_ARG, "unknown MFMA shape");
-  const int layout = shape == MFMA_SHAPE_16X16X32 ? 0 : 1;   // both 32x32x16 kernels share a packing
+  if (!mfma_shape_ok(shape, ctx->m.p))
+    return fail(ctx, PCV_ERR_INVALID_ARG, "unknown MFMA shape, or one the design width does not allow");
+  const int layout = mfma_layout(shape);   // the two 16x16x32 and the two 32x32x16 kernels share packings
   if (!ctx->Xpk_shape[layout]) {
     const int p = static_cast<int>(ctx->m.p);
     const size_t nfr = static_cast<size_t>(ctx->n_tiles) * mfma_nfrag(p, shape) * 64;
@@ -934,7 +936,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   } else if (ctx->path == PATH_MFMA) {
     const int R = mfma_rows_per_tile();
     ctx->n_tiles = static_cast<int>((n + R - 1) / R);
-    const int n_ct = static_cast<int>((C + mfma_chain_tile() - 1) / mfma_chain_tile());
+    const int ct0 = mfma_chain_tile(MFMA_SHAPE_16X16X32);
+    const int n_ct = static_cast<int>((C + ct0 - 1) / ct0);
     // Row splits per chain tile.  One workgroup fits per CU (LDS ring and
     // registers), so workgroups run in rounds of 256; a task costs its tiles
     // plus about four tiles of pipeline fill and partial-result traffic.
@@ -960,7 +963,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
     // non-train row in the tile, or the tile holds padded rows (past n);
     // those waves take the masked epilogue
     {
-      const int cpw = mfma_chain_tile() / 8;   // chains per wave
+      // (k_mfma32's workgroups own 256 chains, like k_mfma's, and only they read the flags)
+      const int cpw = ct0 / 8;   // chains per wave
       std::vector<uint32_t> fl(static_cast<size_t>(ctx->n_tiles) * n_ct, 0u);
       if (n % R != 0)
         for (int c = 0; c < n_ct; ++c) fl[static_cast<size_t>(ctx->n_tiles - 1) * n_ct + c] = 0xFFu;
@@ -974,8 +978,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
           for (int32_t q = test_ptr[k]; q < test_ptr[k + 1]; ++q) tiles.push_back(test_rows[q] / R);
         }
         for (int64_t c = static_cast<int64_t>(kp) * md->L; c < static_cast<int64_t>(kp + 1) * md->L; ++c) {
-          const int cti = static_cast<int>(c / mfma_chain_tile());
-          const uint32_t bit = 1u << static_cast<int>((c % mfma_chain_tile()) / cpw);
+          const int cti = static_cast<int>(c / ct0);
+          const uint32_t bit = 1u << static_cast<int>((c % ct0) / cpw);
           for (int t : tiles) fl[static_cast<size_t>(t) * n_ct + cti] |= bit;
         }
       }
@@ -1854,7 +1858,7 @@ pcv_status apply_splits(pcv_ctx ctx, int ns) {
 constexpr int MFMA_CFG_SHAPE = 256;
 bool mfma_cfg_ok(pcv_ctx ctx, int cfg) {
   const int shape = cfg / MFMA_CFG_SHAPE, ns = cfg % MFMA_CFG_SHAPE;
-  return cfg >= 0 && shape >= MFMA_SHAPE_16X16X32 && shape <= MFMA_SHAPE_32X32X16_IL && ns >= 1 &&
+  return cfg >= 0 && mfma_shape_ok(shape, ctx->m.p) && ns >= 1 &&
          ns <= std::min(64, ctx->n_tiles);
 }
 pcv_status apply_mfma_cfg(pcv_ctx ctx, int cfg) {
@@ -1938,12 +1942,12 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
       if (ns >= 1 && ns <= valu_split_max(ctx) && std::find(cand.begin(), cand.end(), ns) == cand.end())
         cand.push_back(ns);
   } else if (ctx->path == PATH_MFMA) {
-    // both MFMA tile shapes, each with row-split counts around the analytic
-    // choice: config = MFMA_CFG_SHAPE * shape + splits
+    // every MFMA launch shape the width allows, each with row-split counts
+    // around the analytic choice: config = MFMA_CFG_SHAPE * shape + splits
     const int ns0 = ctx->n_splits, hi = std::min(64, ctx->n_tiles);
-    for (int shape : {MFMA_SHAPE_32X32X16, MFMA_SHAPE_32X32X16_IL, MFMA_SHAPE_16X16X32})
+    for (int shape : {MFMA_SHAPE_32X32X16, MFMA_SHAPE_32X32X16_IL, MFMA_SHAPE_16X16X32, MFMA_SHAPE_16X16X32_C16})
       for (int ns : {ns0 / 2, ns0 - 2, ns0 - 1, ns0, ns0 + 1, ns0 + 2, 2 * ns0}) {
-        if (ns < 1 || ns > hi) continue;
+        if (ns < 1 || ns > hi || !mfma_shape_ok(shape, ctx->m.p)) continue;
         const int tps = (ctx->n_tiles + ns - 1) / ns;
         const int nsp = (ctx->n_tiles + tps - 1) / tps;
         const int cfg = MFMA_CFG_SHAPE * shape + nsp;
@@ -2175,6 +2179,8 @@ pcv_status pcv_timing_read(pcv_ctx ctx, double* ms_sum, int64_t* n_launches, con
                        ? "k_mfma32 (bf16 split 32x32x16 MFMA value+gradient)"
                    : ctx->path == PATH_MFMA && ctx->mshape == MFMA_SHAPE_32X32X16_IL
                        ? "k_mfma32 (bf16 split 32x32x16 MFMA value+gradient, free schedule)"
+                   : ctx->path == PATH_MFMA && ctx->mshape == MFMA_SHAPE_16X16X32_C16
+                       ? "k_mfma (bf16 split 16x16x32 MFMA value+gradient, 16 chains per wave)"
                        : kGradKernelName[ctx->path];
   if (reset) {
     ctx->ms_acc = 0.0;

@@ -35,6 +35,8 @@ constexpr int MF_ROWS = 32;                                   // rows per tile
 // zero columns past p, theta is taken as zero there, and only the first p
 // gradient rows are written, so any 1 <= p <= 128 runs on the P kernels.
 int mfma_width(int64_t p) { return p <= 64 ? 64 : 128; }
+int mfma_chain_tile(int shape);
+int mfma_layout(int shape);
 
 // fragments per 32-row tile: forward 2 (M) x P/32 (K) x 2 planes, adjoint P/16 (M) x 2 planes
 __host__ __device__ constexpr int mf_nfrag_fwd(int P) { return 2 * (P / 32) * 2; }
@@ -103,8 +105,62 @@ __device__ __forceinline__ void mf_resid_ell0(float y, float e2, float is2, floa
   }
 }
 
-template <int FAM, int P, int FWD, bool VALUE, int FK>
-__global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
+// theta[j][c] at the 8 KB coordinates j = KS kb + off + e (kb < KB, e < 8)
+// of chain c, split into NT bf16 terms (the MFMA B operand; pre-scaled by
+// log2 e for the logistic and Poisson families).  Coordinates past p (the
+// design's zero columns up to the kernel's width) and coordinates a nested
+// model drops take theta = 0.  Every load is unconditional, from a clamped
+// chain and coordinate, and the selection comes after: a guarded load would
+// become a branch with a wait of its own, and the lane's loads would run
+// one round trip at a time instead of all in flight together.
+template <int FAM, int NT, int KB, int KS, bool MASKED>
+__device__ __forceinline__ void mf_theta_terms(const DevModel& m, int64_t c, int off, bf16x8 (&out)[NT][KB]) {
+  const bool cv = c < m.C;
+  const int64_t cc = cv ? c : m.C - 1;
+  const uint8_t* mrow = MASKED ? mask_row(m, cc) : nullptr;
+  double tv[KB][8];
+  bool keep[KB][8];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int j = KS * kb + off + e;
+      const int jc = j < m.p ? j : static_cast<int>(m.p) - 1;
+      tv[kb][e] = m.q1[static_cast<int64_t>(jc) * m.C + cc];
+      const uint8_t mb = MASKED ? mrow[jc] : 1;
+      keep[kb][e] = cv & (j < m.p) & (mb != 0);
+    }
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const double t = keep[kb][e] ? tv[kb][e] * mf_theta_scale<FAM>() : 0.0;
+      if (NT == 2) {
+        const float t32 = static_cast<float>(t);
+        const __bf16 h = to_bf16(t32);
+        out[0][kb][e] = h;
+        out[1][kb][e] = to_bf16(t32 - static_cast<float>(h));
+      } else {
+        const __bf16 h = to_bf16(static_cast<float>(t));
+        const double r1 = t - static_cast<double>(static_cast<float>(h));
+        const __bf16 mdl = to_bf16(static_cast<float>(r1));
+        const double r2 = r1 - static_cast<double>(static_cast<float>(mdl));
+        out[0][kb][e] = h;
+        out[1][kb][e] = mdl;
+        out[NT - 1][kb][e] = to_bf16(static_cast<float>(r2));
+      }
+    }
+}
+
+// CB = 16-chain blocks per wave: 2 (32 chains per wave, 256 per workgroup,
+// one workgroup per CU) or 1 (16 chains per wave, 128 per workgroup; at
+// P = 64 the registers then fit two workgroups per CU, four waves per SIMD,
+// at the cost of twice the fragment reads per MFMA).
+template <int FAM, int P, int FWD, bool VALUE, int FK, int CB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CB == 1 ? 4 : 1))) void k_mfma(MfmaArgs a) {
+  static_assert(CB == 2 || (CB == 1 && P == 64), "16 chains per wave only at width 64");
+  constexpr int CPW = 16 * CB;                    // chains per wave
+  constexpr int CT = MF_WAVES * CPW;              // chains per workgroup
   constexpr int KB = P / 32;
   constexpr int MB = P / 16;
   constexpr int NFF = mf_nfrag_fwd(P);
@@ -130,20 +186,20 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   // tasks split-major: the workgroups resident on one XCD then share a row
   // split and stream the same X tiles through that XCD's L2 together.
   const int task = mf_xcd_task(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
-  const int n_ct = static_cast<int>((m.C + MF_CHAIN_TILE - 1) / MF_CHAIN_TILE);
+  const int n_ct = static_cast<int>((m.C + CT - 1) / CT);
   const int sp = task / n_ct;
   const int ct = task - sp * n_ct;
-  const int64_t cbase = static_cast<int64_t>(ct) * MF_CHAIN_TILE + wave * MF_CHAINS_PER_WAVE;
+  const int64_t cbase = static_cast<int64_t>(ct) * CT + wave * CPW;
   const bool wave_active = cbase < m.C;
   const int t_beg = sp * a.tiles_per_split;
   const int t_end = min(a.n_tiles, t_beg + a.tiles_per_split);
   const int t_last = t_end > t_beg ? t_end - 1 : t_beg;
 
-  // chains of this lane in its two 16-chain blocks
-  int kf[2], elo[2], ehi[2];
-  int64_t cidx[2];
+  // chains of this lane in its CB 16-chain blocks
+  int kf[CB], elo[CB], ehi[CB];
+  int64_t cidx[CB];
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
+  for (int cb = 0; cb < CB; ++cb) {
     const int64_t c = cbase + cb * 16 + l16;
     cidx[cb] = c;
     const int64_t cc = c < m.C ? c : m.C - 1;
@@ -157,45 +213,26 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   }
 
   // theta operand fragments: lane holds theta[k = kb*32 + 8*g4 + e][chain]
-  bf16x8 th[NT][KB][2];
+  bf16x8 th[NT][KB][CB];
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    const int64_t c = cidx[cb];
-    const bool cv = c < m.C;
-    const uint8_t* mrow = cv ? mask_row(m, c) : nullptr;
+  for (int cb = 0; cb < CB; ++cb) {
+    bf16x8 t[NT][KB];
+    if (m.mmask) mf_theta_terms<FAM, NT, KB, 32, true>(m, cidx[cb], 8 * g4, t);
+    else mf_theta_terms<FAM, NT, KB, 32, false>(m, cidx[cb], 8 * g4, t);
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
+    for (int q = 0; q < NT; ++q)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        // coordinates past p (the design's zero columns up to the kernel's
-        // width P) and coordinates a nested model drops take theta = 0
-        const int j = kb * 32 + 8 * g4 + e;
-        const bool used = cv && j < m.p && (!mrow || mrow[j]);
-        const double t = used ? m.q1[static_cast<int64_t>(j) * m.C + c] * mf_theta_scale<FAM>() : 0.0;
-        if (NT == 2) {
-          const float t32 = static_cast<float>(t);
-          const __bf16 h = to_bf16(t32);
-          th[0][kb][cb][e] = h;
-          th[1][kb][cb][e] = to_bf16(t32 - static_cast<float>(h));
-        } else {
-          const __bf16 h = to_bf16(static_cast<float>(t));
-          const double r1 = t - static_cast<double>(static_cast<float>(h));
-          const __bf16 mdl = to_bf16(static_cast<float>(r1));
-          const double r2 = r1 - static_cast<double>(static_cast<float>(mdl));
-          th[0][kb][cb][e] = h;
-          th[1][kb][cb][e] = mdl;
-          th[NT - 1][kb][cb][e] = to_bf16(static_cast<float>(r2));
-        }
-      }
-    }
+      for (int kb = 0; kb < KB; ++kb) th[q][kb][cb] = t[q][kb];
   }
 
-  f32x4 gacc[MB][2];
+  f32x4 gacc[MB][CB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) gacc[mb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  double vacc[2] = {0.0, 0.0};
+    for (int cb = 0; cb < CB; ++cb) gacc[mb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double vacc[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) vacc[cb] = 0.0;
   const float is2 = static_cast<float>(m.inv_sigma2);
   const int nrows = static_cast<int>(m.n);
 
@@ -227,12 +264,12 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
     sf[b][tid & (MF_ROWS - 1)] = my_f;
   };
 
-  // forward product of one tile (buffer b): eta[32 rows x 32 chains]
-  auto forward = [&](int b, f32x4 (&eta)[2][2]) {
+  // forward product of one tile (buffer b): eta[32 rows x CPW chains]
+  auto forward = [&](int b, f32x4 (&eta)[2][CB]) {
 #pragma unroll
     for (int mh = 0; mh < 2; ++mh)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) eta[mh][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int cb = 0; cb < CB; ++cb) eta[mh][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
 #pragma unroll
@@ -241,7 +278,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
         const bf16x8 x0 = __builtin_bit_cast(bf16x8, sfrag[b][f * 64 + lane]);
         const bf16x8 x1 = __builtin_bit_cast(bf16x8, sfrag[b][(f + 1) * 64 + lane]);
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < CB; ++cb) {
           f32x4 acc = eta[mh][cb];
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, th[0][kb][cb], acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, th[1][kb][cb], acc, 0, 0, 0);
@@ -259,12 +296,12 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   // The per-tile work is cut into NG groups that alternate between the
   // forward product of the next tile (group 2q: K block q/2.. of M half) and
   // the adjoint product of the previous tile (group 2q+1: M block q), each
-  // group = two fragment reads + 6 (or 10) MFMAs, with EPG epilogue
+  // group = two fragment reads + 3 CB (or 5 CB) MFMAs, with EPG epilogue
   // elements of the current tile in between.  The three streams are
   // independent, so the order is pinned with scheduling barriers.
   constexpr int NG = 2 * MB;            // = 2 * (2 * KB)
-  constexpr int EPG = 16 / NG;          // epilogue elements per group
-  static_assert(EPG * NG == 16, "16 epilogue elements per lane per tile");
+  constexpr int EPG = 8 * CB / NG;      // epilogue elements per group
+  static_assert(EPG * NG == 8 * CB, "8 CB epilogue elements per lane per tile");
 
   auto frag = [&](int b, int f) { return __builtin_bit_cast(bf16x8, sfrag[b][f * 64 + lane]); };
   auto group_frag_index = [&](int g) {
@@ -284,11 +321,11 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   store_stage(1);
   load_stage(min(t_beg + 2, t_last));
   __syncthreads();
-  f32x4 eta_cur[2][2], eta_nxt[2][2];
+  f32x4 eta_cur[2][CB], eta_nxt[2][CB];
   forward(0, eta_cur);
-  bf16x8 rph[2], rpl[2], rch[2], rcl[2];   // residual fragments: previous / current tile
+  bf16x8 rph[CB], rpl[CB], rch[CB], rcl[CB];   // residual fragments: previous / current tile
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
+  for (int cb = 0; cb < CB; ++cb) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       rph[cb][e] = to_bf16(0.f);
@@ -318,8 +355,10 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
 #pragma unroll
     for (int mh = 0; mh < 2; ++mh)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) eta_nxt[mh][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float vt[2] = {0.f, 0.f};
+      for (int cb = 0; cb < CB; ++cb) eta_nxt[mh][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float vt[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) vt[cb] = 0.f;
 
     bf16x8 xa0 = frag(b1, group_frag_index(0)), xa1 = frag(b1, group_frag_index(0) + 1);
 #pragma unroll
@@ -334,7 +373,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
       if ((g & 1) == 0) {
         const int q = g >> 1, mh = q / KB, kb = q % KB;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < CB; ++cb) {
           f32x4 acc = eta_nxt[mh][cb];
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, th[0][kb][cb], acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, th[1][kb][cb], acc, 0, 0, 0);
@@ -348,7 +387,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
       } else {
         const int mb = g >> 1;
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < CB; ++cb) {
           f32x4 acc = gacc[mb][cb];
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, rph[cb], acc, 0, 0, 0);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa0, rpl[cb], acc, 0, 0, 0);
@@ -360,7 +399,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
 #pragma unroll
       for (int u = 0; u < EPG; ++u) {
         const int el = g * EPG + u;
-        const int e = el >> 1, cb = el & 1;
+        const int e = el / CB, cb = el % CB;
         const int mh = e >> 2, ii = e & 3;
         const int row = tt * MF_ROWS + mh * 16 + 4 * g4 + ii;
         // padded rows (row >= n) hold X = 0, so they add nothing to G; only
@@ -384,18 +423,18 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
       xa1 = xb1;
     }
     if (VALUE) {
-      vacc[0] += static_cast<double>(vt[0]);
-      vacc[1] += static_cast<double>(vt[1]);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) vacc[cb] += static_cast<double>(vt[cb]);
     }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
       rph[cb] = rch[cb];
       rpl[cb] = rcl[cb];
     }
 #pragma unroll
     for (int mh = 0; mh < 2; ++mh)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) eta_cur[mh][cb] = eta_nxt[mh][cb];
+      for (int cb = 0; cb < CB; ++cb) eta_cur[mh][cb] = eta_nxt[mh][cb];
   }
   // adjoint of the last tile (its slot is untouched since it was loaded)
   {
@@ -404,7 +443,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
     for (int mb = 0; mb < MB; ++mb) {
       const bf16x8 x0 = frag(bl, NFF + mb * 2), x1 = frag(bl, NFF + mb * 2 + 1);
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
+      for (int cb = 0; cb < CB; ++cb) {
         f32x4 acc = gacc[mb][cb];
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, rph[cb], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, rpl[cb], acc, 0, 0, 0);
@@ -417,7 +456,7 @@ __global__ __launch_bounds__(512) void k_mfma(MfmaArgs a) {
   if (!wave_active) return;
   // ---- partial results -----------------------------------------------------
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
+  for (int cb = 0; cb < CB; ++cb) {
     const int64_t c = cidx[cb];
     if (c < m.C) {
 #pragma unroll
@@ -535,32 +574,8 @@ __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
 
   // theta as the B operand: lane holds theta[16 kb + 8 hh + e][chain]
   bf16x8 th[NT][KB];
-  {
-    const uint8_t* mrow = cvalid ? mask_row(m, cidx) : nullptr;
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = kb * 16 + 8 * hh + e;
-        const bool used = cvalid && j < m.p && (!mrow || mrow[j]);
-        const double t = used ? m.q1[static_cast<int64_t>(j) * m.C + cidx] * mf_theta_scale<FAM>() : 0.0;
-        if (NT == 2) {
-          const float t32 = static_cast<float>(t);
-          const __bf16 h = to_bf16(t32);
-          th[0][kb][e] = h;
-          th[1][kb][e] = to_bf16(t32 - static_cast<float>(h));
-        } else {
-          const __bf16 h = to_bf16(static_cast<float>(t));
-          const double r1 = t - static_cast<double>(static_cast<float>(h));
-          const __bf16 mdl = to_bf16(static_cast<float>(r1));
-          const double r2 = r1 - static_cast<double>(static_cast<float>(mdl));
-          th[0][kb][e] = h;
-          th[1][kb][e] = mdl;
-          th[NT - 1][kb][e] = to_bf16(static_cast<float>(r2));
-        }
-      }
-    }
-  }
+  if (m.mmask) mf_theta_terms<FAM, NT, KB, 16, true>(m, cidx, 8 * hh, th);
+  else mf_theta_terms<FAM, NT, KB, 16, false>(m, cidx, 8 * hh, th);
 
   f32x16 gacc[MB];
 #pragma unroll
@@ -882,9 +897,12 @@ static hipError_t launch_mfma_p(const MfmaArgs& a, bool value, int nblk, hipStre
       else hipLaunchKernelGGL((KERN<FAM, P, FWD, false, PCV_FOLDS_INDEX __VA_ARGS__>), dim3(nblk), dim3(512), 0, st, a);       \
     }                                                                                                    \
   } while (0)
-  if (SHAPE == MFMA_SHAPE_32X32X16) PCV_MFMA_LAUNCH(k_mfma32, , 0);
-  else if (SHAPE == MFMA_SHAPE_32X32X16_IL) PCV_MFMA_LAUNCH(k_mfma32, , 1);
-  else PCV_MFMA_LAUNCH(k_mfma);
+  if constexpr (SHAPE == MFMA_SHAPE_32X32X16) PCV_MFMA_LAUNCH(k_mfma32, , 0);
+  else if constexpr (SHAPE == MFMA_SHAPE_32X32X16_IL) PCV_MFMA_LAUNCH(k_mfma32, , 1);
+  else if constexpr (SHAPE == MFMA_SHAPE_16X16X32_C16) {
+    if constexpr (P == 64) PCV_MFMA_LAUNCH(k_mfma, , 1);
+    else return hipErrorInvalidValue;
+  } else PCV_MFMA_LAUNCH(k_mfma, , 2);
 #undef PCV_MFMA_LAUNCH
   return hipGetLastError();
 }
@@ -922,28 +940,37 @@ hipError_t launch_mfma(const DevModel& m, int shape, const uint4* Xpk, const flo
   a.n_tiles = n_tiles;
   a.tiles_per_split = tiles_per_split;
   a.n_splits = n_splits;
-  const int n_ct = static_cast<int>((m.C + MF_CHAIN_TILE - 1) / MF_CHAIN_TILE);
+  const int ct = mfma_chain_tile(shape);
+  const int n_ct = static_cast<int>((m.C + ct - 1) / ct);
   const int nblk = n_ct * n_splits;
   const int P = mfma_width(m.p);
   if (shape == MFMA_SHAPE_32X32X16) return launch_mfma_s<MFMA_SHAPE_32X32X16>(a, P, fwd, value, nblk, st);
   if (shape == MFMA_SHAPE_32X32X16_IL) return launch_mfma_s<MFMA_SHAPE_32X32X16_IL>(a, P, fwd, value, nblk, st);
   if (shape == MFMA_SHAPE_16X16X32) return launch_mfma_s<MFMA_SHAPE_16X16X32>(a, P, fwd, value, nblk, st);
+  if (shape == MFMA_SHAPE_16X16X32_C16 && P == 64)
+    return launch_mfma_s<MFMA_SHAPE_16X16X32_C16>(a, P, fwd, value, nblk, st);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_mfma_pack(const double* X, int64_t n, int p, int n_tiles, int shape, uint4* out, hipStream_t st) {
   const int P = mfma_width(p);
-  if (shape != MFMA_SHAPE_16X16X32)
+  if (mfma_layout(shape) == 1)
     hipLaunchKernelGGL(k_mfma32_pack, dim3(1024), dim3(256), 0, st, X, n, p, P, n_tiles, out);
   else hipLaunchKernelGGL(k_mfma_pack, dim3(1024), dim3(256), 0, st, X, n, p, P, n_tiles, out);
   return hipGetLastError();
 }
 
-int mfma_chain_tile() { return MF_CHAIN_TILE; }
+int mfma_chain_tile(int shape) { return shape == MFMA_SHAPE_16X16X32_C16 ? MF_CHAIN_TILE / 2 : MF_CHAIN_TILE; }
 int mfma_rows_per_tile() { return MF_ROWS; }
+// X packing of a shape: 0 = the 16x16x32 kernels' fragment orders, 1 = the 32x32x16 kernels'
+int mfma_layout(int shape) { return shape == MFMA_SHAPE_32X32X16 || shape == MFMA_SHAPE_32X32X16_IL ? 1 : 0; }
+bool mfma_shape_ok(int shape, int64_t p) {
+  return shape >= MFMA_SHAPE_16X16X32 && shape <= MFMA_SHAPE_16X16X32_C16 &&
+         (shape != MFMA_SHAPE_16X16X32_C16 || mfma_width(p) == 64);
+}
 int mfma_nfrag(int p, int shape) {
   const int P = mfma_width(p);
-  return shape != MFMA_SHAPE_16X16X32 ? m2_nfrag(P) : mf_nfrag(P);
+  return mfma_layout(shape) == 1 ? m2_nfrag(P) : mf_nfrag(P);
 }
 
 }  // namespace pcv

@@ -142,7 +142,9 @@ __host__ __device__ constexpr bool hier_family(int fam) { return fam == FAM_HIER
 constexpr double HGAUSS_SCALE_VAR = 10.0;
 // MFMA tile shapes of the matrix-core gradient kernel (a launch-shape knob)
 // (MFMA_SHAPE_32X32X16_IL: the 32x32x16 kernel scheduled by the compiler across groups)
-enum { MFMA_SHAPE_16X16X32 = 0, MFMA_SHAPE_32X32X16 = 1, MFMA_SHAPE_32X32X16_IL = 2 };
+// (MFMA_SHAPE_16X16X32_C16: the 16x16x32 kernel with 16 chains per wave, two
+// workgroups per CU; design widths p <= 64 only)
+enum { MFMA_SHAPE_16X16X32 = 0, MFMA_SHAPE_32X32X16 = 1, MFMA_SHAPE_32X32X16_IL = 2, MFMA_SHAPE_16X16X32_C16 = 3 };
 
 // d l(y, eta) / d eta and l(y, eta) minus its per-row constant.
 // (FAM_HGAUSS: the Gaussian forms with the chain's own 1/sigma_y^2; its

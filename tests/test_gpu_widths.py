@@ -3,7 +3,7 @@ MI355X).  The bf16 kernels are built for widths 64 and 128; a design of
 1 <= p <= 128 columns runs on the next one with zero columns past p, zero
 coefficients there, and only the first p gradient rows written.  Checked
 against the oracle like the full-width cases: the log density and gradient
-of every chain in both tile shapes and several row-split counts, leapfrog
+of every chain in three launch shapes and several row-split counts, leapfrog
 trajectories, and two nested models in one launch at an odd width (their
 selection masks are read per coefficient)."""
 import numpy as np
@@ -68,9 +68,11 @@ WIDTHS = [("c4", 1, (0, 16)), ("c4", 17, (0, 16)), ("c4", 40, (0, 16)), ("c5", 6
           ("c5", 100, (100, 140))]
 
 
-@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("shape", [0, 1, 3])
 @pytest.mark.parametrize("name,p,folds_", WIDTHS)
 def test_any_width_matches_oracle(dev, shape, name, p, folds_):
+    if shape == 3 and p > 64:
+        pytest.skip("the 16-chain shape is for designs of up to 64 columns")
     w = _narrow(name, p, folds_)
     assert w.p == p and w.x_hi.shape[1] == p
     theta = _theta(w, seed=8)
@@ -98,7 +100,7 @@ def test_any_width_matches_oracle(dev, shape, name, p, folds_):
     s.close()
 
 
-@pytest.mark.parametrize("shape", [0, 1])
+@pytest.mark.parametrize("shape", [0, 1, 3])
 @pytest.mark.parametrize("name,p,folds_", WIDTHS)
 def test_any_width_equals_the_zero_padded_design(dev, shape, name, p, folds_):
     """The narrow design against the same design padded to the kernel width
@@ -106,6 +108,8 @@ def test_any_width_equals_the_zero_padded_design(dev, shape, name, p, folds_):
     shape: the first p gradient entries agree bit for bit, the padded ones
     are zero, and the log densities differ by the padded coefficients'
     prior terms at zero."""
+    if shape == 3 and p > 64:
+        pytest.skip("the 16-chain shape is for designs of up to 64 columns")
     full = W.fold_subset(W.make(name), *folds_)
     P = 64 if p <= 64 else 128
     w = _narrow(name, p, folds_)
