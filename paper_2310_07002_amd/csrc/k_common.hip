@@ -111,11 +111,24 @@ __global__ __launch_bounds__(64 * accept_max_y<FAM>()) void k_accept(DevModel m,
   if (t < 0) t = *m.t_dev;
   double v = 0.0, pq = 0.0, k1 = 0.0, lp = 0.0;
   for (int s = y; s < n_splits; s += Y) v += Vpart[static_cast<int64_t>(s) * m.C + cc];
-  for (int64_t j = y; j < m.d; j += Y) {
-    const int64_t o = j * m.C + cc;
-    pq += prior_term(m, m.q1[o], j);
-    const double p = m.pm[o];
-    k1 += 0.5 * m.minv[j] * p * p;
+  // coordinates y, y + Y, ... in batches of four: loads from clamped indices
+  // first (all in flight), then the sums in coordinate order
+  for (int64_t j0 = y; j0 < m.d; j0 += 4 * Y) {
+    double qv[4], pv[4], mv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t j = j0 + u * Y < m.d ? j0 + u * Y : j0;
+      const int64_t o = j * m.C + cc;
+      qv[u] = m.q1[o];
+      pv[u] = m.pm[o];
+      mv[u] = m.minv[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + u * Y < m.d) {
+        pq += prior_term(m, qv[u], j0 + u * Y);
+        k1 += 0.5 * mv[u] * pv[u] * pv[u];
+      }
   }
   const int k = fold_of_chain(m, cc);
   // the hierarchical Gaussian's -n_train log sigma_y (prior_quad's extra term)
@@ -129,7 +142,9 @@ __global__ __launch_bounds__(64 * accept_max_y<FAM>()) void k_accept(DevModel m,
   red[3][y][lane] = lp;
   __syncthreads();
   bool accepted = false, divergent = false;
+  double s_sel = 0.0;   // log predictive of the selected state (wave 0)
   if (y == 0) {
+    const double s_prev = m.s0[cc];
     v = pq = k1 = lp = 0.0;
     for (int w = 0; w < Y; ++w) {
       v += red[0][w][lane];
@@ -140,24 +155,36 @@ __global__ __launch_bounds__(64 * accept_max_y<FAM>()) void k_accept(DevModel m,
     if (valid) {
       const double logp1 = v + m.fold_const[k] + pq;
       m.logp1[c] = logp1;
-      metropolis(m, c, t, k1, accepted, divergent);
+      metropolis(m, c, t, logp1, k1, accepted, divergent);
       if (accepted) {
         m.logp0[c] = logp1;
         m.s0[c] = lp;
       }
+      s_sel = accepted ? lp : s_prev;
     }
     acc_s[lane] = accepted ? 1 : 0;
   }
   __syncthreads();
   if (valid && acc_s[lane]) {
-    for (int64_t j = y; j < m.d; j += Y) {
-      const int64_t o = j * m.C + c;
-      m.q0[o] = m.q1[o];
-      m.g0[o] = m.g1[o];
+    // batches of four coordinates: loads first, then the stores
+    for (int64_t j0 = y; j0 < m.d; j0 += 4 * Y) {
+      double qv[4], gv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + u * Y < m.d ? j0 + u * Y : j0;
+        qv[u] = m.q1[j * m.C + c];
+        gv[u] = m.g1[j * m.C + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j0 + u * Y < m.d) {
+          m.q0[(j0 + u * Y) * m.C + c] = qv[u];
+          m.g0[(j0 + u * Y) * m.C + c] = gv[u];
+        }
     }
   }
   __syncthreads();
-  if (y == 0 && valid) record_draw<FAM>(m, c, t, accepted, divergent);
+  if (y == 0 && valid) record_draw<FAM>(m, c, t, accepted, divergent, s_sel);
 }
 
 // Log predictive at q0 for every chain (initialisation and set_state).

@@ -93,10 +93,7 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
 
   const int32_t* wr = wave_rows ? wave_rows : m.wave_rows;
   T th[PB];
-  const uint8_t* mrow = mask_row(m, cc);
-#pragma unroll
-  for (int j = 0; j < PB; ++j)
-    th[j] = (j < m.p && covariate_used(mrow, j)) ? static_cast<T>(m.q1[j * m.C + cc]) : T(0);
+  theta_row<PB>(m, m.q1, cc, th);
   T mu = 0;
   if (hier_fam<FAM>()) {
     // tau z_g only for the groups of this workgroup's rows; rg cleared for all

@@ -199,6 +199,32 @@ __device__ __forceinline__ const uint8_t* mask_row(const DevModel& m, int64_t c)
 }
 __device__ __forceinline__ bool covariate_used(const uint8_t* row, int64_t j) { return !row || row[j] != 0; }
 
+// Coefficients j < PB of chain c at position q ([d][C]), zero at j >= p and
+// where the chain's model drops j.  Every load is unconditional (clamped
+// index; the selection comes after), so all of them are in flight at once: a
+// load under a per-lane condition compiles to a branch that waits for that
+// load alone.
+template <int PB, typename T>
+__device__ __forceinline__ void theta_row(const DevModel& m, const double* q, int64_t c, T (&th)[PB]) {
+  double tv[PB];
+  bool keep[PB];
+#pragma unroll
+  for (int j = 0; j < PB; ++j) {
+    tv[j] = q[(j < m.p ? j : m.p - 1) * m.C + c];
+    keep[j] = j < m.p;
+  }
+  if (m.mmask) {
+    const uint8_t* mrow = mask_row(m, c);
+    uint8_t mb[PB];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) mb[j] = mrow[j < m.p ? j : m.p - 1];
+#pragma unroll
+    for (int j = 0; j < PB; ++j) keep[j] = keep[j] && mb[j] != 0;
+  }
+#pragma unroll
+  for (int j = 0; j < PB; ++j) th[j] = keep[j] ? static_cast<T>(tv[j]) : T(0);
+}
+
 // Role of row i in fold k: 0 excluded, 1 train, 2 test.
 __device__ __forceinline__ int row_role(const DevModel& m, int64_t i, int k) {
   if (m.fold_kind == PCV_FOLDS_INDEX) {
@@ -235,8 +261,8 @@ __device__ __forceinline__ double eta_row64(const DevModel& m, const double* q, 
 
 // Log density (fp64, with constants) of test slots [a0, a1) of chain c's
 // fold at q; the group location and scale are read once.
-template <int FAM>
-__device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, int a0, int a1) {
+template <int FAM, bool MASKED>
+__device__ double log_pred_rows_m(const DevModel& m, const double* q, int64_t c, int a0, int a1) {
   double mu = 0.0, tau = 0.0, is2 = m.inv_sigma2, lsy = 0.0;
   const int64_t z0 = hier_z0(m);
   if (hier_fam<FAM>()) {
@@ -247,19 +273,27 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
     lsy = q[(m.p + 2) * m.C + c];
     is2 = exp(-2.0 * lsy);
   }
-  const uint8_t* mrow = mask_row(m, c);
+  const uint8_t* mrow = MASKED ? mask_row(m, c) : nullptr;
+  // coefficient j of the chain, zero where its model drops j (loads first,
+  // unconditionally, then the selection: a guarded load waits alone)
+  auto coef = [&](int64_t j) {
+    const double v = q[j * m.C + c];
+    if (!MASKED) return v;
+    const uint8_t keep = mrow[j];
+    return keep ? v : 0.0;
+  };
   double s = 0.0;
   // Four rows at a time (a last group of two or three masked, a last single
   // row on its own), LPB coefficients per batch of loads, so that loads
   // overlap; each row's arithmetic and the order of the sum over rows are
   // those of a plain row-by-row loop.
-  constexpr int LPB = 2;
+  constexpr int LPB = 4;
   for (int t = a0; t < a1; t += 4) {
     if (t + 1 == a1) {
       const int64_t i = m.test_rows[t];
       const double* x = m.X64 + i * m.p;
       double e = 0.0;
-      for (int64_t j = 0; j < m.p; ++j) e += x[j] * (covariate_used(mrow, j) ? q[j * m.C + c] : 0.0);
+      for (int64_t j = 0; j < m.p; ++j) e += x[j] * coef(j);
       if (hier_fam<FAM>()) e += mu + tau * q[(z0 + m.group_of[i]) * m.C + c];
       s += ell0_64<FAM>(m.y64[i], e, is2) + m.rowc[i] - lsy;
       break;
@@ -276,7 +310,7 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
 #pragma unroll
       for (int v = 0; v < LPB; ++v) {
         const int64_t j = j0 + v < m.p ? j0 + v : j0;
-        qj[v] = covariate_used(mrow, j) ? q[j * m.C + c] : 0.0;
+        qj[v] = coef(j);
 #pragma unroll
         for (int u = 0; u < 4; ++u) xv[u][v] = m.X64[i[u] * m.p + j];
       }
@@ -296,6 +330,10 @@ __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, i
     }
   }
   return s;
+}
+template <int FAM>
+__device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, int a0, int a1) {
+  return m.mmask ? log_pred_rows_m<FAM, true>(m, q, c, a0, a1) : log_pred_rows_m<FAM, false>(m, q, c, a0, a1);
 }
 
 // Joint log density of the fold's test rows at q (fp64, with constants).
@@ -411,33 +449,43 @@ __device__ __forceinline__ void leapfrog_update(const DevModel& m, int64_t c, in
 }
 
 // Welford (or shifted-sum) / log-sum-exp accumulation of post-warm-up draw i
-// (Algorithm A2).
+// (Algorithm A2).  The chain's accumulators are all read before any is
+// written, so their loads are in flight together.
 __device__ __forceinline__ void accumulate_draw(const DevModel& m, int64_t c, int64_t i, double s) {
-  m.Z[c] = log_add_exp(m.Z[c], s);
-  m.U2[c] = log_add_exp(m.U2[c], 2.0 * s);
   const int64_t per_block = static_cast<int64_t>(m.Gb) * m.b;
   int64_t blk = i / per_block;
   if (blk > m.D - 1) blk = m.D - 1;
   const double cnt = static_cast<double>(i - blk * per_block + 1);
   const int64_t o = blk * m.C + c;
+  const bool batch_end = (i + 1) % m.b == 0;
+  const double z0 = m.Z[c], u20 = m.U2[c], mean = m.bmean[o], m2 = m.bm2[o];
+  const double ctr = m.center[c / m.L];   // read in both modes (the shifted-sums centre)
+  double u0 = 0.0, v0 = 0.0, v20 = 0.0;
+  if (batch_end) {
+    u0 = m.U[c];
+    v0 = m.V[c];
+    v20 = m.V2[c];
+  }
+  const double z = log_add_exp(z0, s);
+  m.U2[c] = log_add_exp(u20, 2.0 * s);
   if (m.rhat_mode == 1) {
-    const double dv = s - m.center[c / m.L];
-    m.bmean[o] += dv;
-    m.bm2[o] += dv * dv;
+    const double dv = s - ctr;
+    m.bmean[o] = mean + dv;
+    m.bm2[o] = m2 + dv * dv;
   } else {
-    const double mean = m.bmean[o];
     const double delta = s - mean;
     const double nm = mean + delta / cnt;
     m.bmean[o] = nm;
-    m.bm2[o] += delta * (s - nm);
+    m.bm2[o] = m2 + delta * (s - nm);
   }
-  if ((i + 1) % m.b == 0) {
-    const double z = m.Z[c];
+  if (batch_end) {
     const double lb = log(static_cast<double>(m.b));
-    m.U[c] = log_add_exp(m.U[c], z);
-    m.V[c] = log_add_exp(m.V[c], z - lb);
-    m.V2[c] = log_add_exp(m.V2[c], 2.0 * z - 2.0 * lb);
+    m.U[c] = log_add_exp(u0, z);
+    m.V[c] = log_add_exp(v0, z - lb);
+    m.V2[c] = log_add_exp(v20, 2.0 * z - 2.0 * lb);
     m.Z[c] = -INFINITY;
+  } else {
+    m.Z[c] = z;
   }
 }
 
@@ -498,11 +546,11 @@ __device__ void accumulate_scores(const DevModel& m, int64_t c, int64_t t) {
   }
 }
 
-// Metropolis test of chain c at transition t, given the kinetic energy k1 at
-// the end of its trajectory (logp1 already set).
-__device__ __forceinline__ void metropolis(const DevModel& m, int64_t c, int64_t t, double k1, bool& accepted,
-                                           bool& divergent) {
-  const double h1 = -m.logp1[c] + k1;
+// Metropolis test of chain c at transition t, given log pi and the kinetic
+// energy k1 at the end of its trajectory.
+__device__ __forceinline__ void metropolis(const DevModel& m, int64_t c, int64_t t, double logp1, double k1,
+                                           bool& accepted, bool& divergent) {
+  const double h1 = -logp1 + k1;
   const double log_ratio = m.h0[c] - h1;
   const uint32_t gc = static_cast<uint32_t>(m.chain_offset + c);
   const W4 w = philox4x32_10(W4{gc, static_cast<uint32_t>(t), TAG_ACCEPT, 0u}, m.key0, m.key1);
@@ -516,16 +564,18 @@ __device__ __forceinline__ void metropolis(const DevModel& m, int64_t c, int64_t
 // Bookkeeping of transition t once the state (q0, s0) is selected: warm-up
 // sums, or the online accumulators, scores, stored draw and counters.
 template <int FAM>
-__device__ void record_draw(const DevModel& m, int64_t c, int64_t t, bool accepted, bool divergent) {
+// s0 is the log predictive of the selected state (the value s0[c] holds).
+__device__ void record_draw(const DevModel& m, int64_t c, int64_t t, bool accepted, bool divergent, double s0) {
   if (t < m.n_warmup) {
-    if (m.rhat_mode == 1) m.wsum[c] += m.s0[c];
+    if (m.rhat_mode == 1) m.wsum[c] += s0;
   } else {
-    accumulate_draw(m, c, t - m.n_warmup, m.s0[c]);
+    const int64_t na = m.nacc[c], nd = m.ndiv[c];   // read before the accumulators are written
+    accumulate_draw(m, c, t - m.n_warmup, s0);
     if (m.scores) accumulate_scores<FAM>(m, c, t);
     const int64_t di = t - m.n_warmup;
-    if (m.draws && di < m.draws_cap) m.draws[di * m.C + c] = m.s0[c];
-    m.nacc[c] += accepted ? 1 : 0;
-    m.ndiv[c] += divergent ? 1 : 0;
+    if (m.draws && di < m.draws_cap) m.draws[di * m.C + c] = s0;
+    m.nacc[c] = na + (accepted ? 1 : 0);
+    m.ndiv[c] = nd + (divergent ? 1 : 0);
   }
 }
 
@@ -539,7 +589,8 @@ __device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
     k1 += 0.5 * m.minv[j] * p * p;
   }
   bool accepted, divergent;
-  metropolis(m, c, t, k1, accepted, divergent);
+  metropolis(m, c, t, m.logp1[c], k1, accepted, divergent);
+  double s0;
   if (accepted) {
     for (int64_t j = 0; j < m.d; ++j) {
       const int64_t o = j * m.C + c;
@@ -547,9 +598,12 @@ __device__ void accept_and_accumulate(const DevModel& m, int64_t c, int64_t t) {
       m.g0[o] = m.g1[o];
     }
     m.logp0[c] = m.logp1[c];
-    m.s0[c] = log_pred_fold<FAM>(m, m.q0, c);
+    s0 = log_pred_fold<FAM>(m, m.q0, c);
+    m.s0[c] = s0;
+  } else {
+    s0 = m.s0[c];
   }
-  record_draw<FAM>(m, c, t, accepted, divergent);
+  record_draw<FAM>(m, c, t, accepted, divergent, s0);
 }
 
 }  // namespace pcv
