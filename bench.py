@@ -62,7 +62,7 @@ def baseline_folds(w) -> int:
     folds x 8 chains of the Poisson GLM and 50 folds x 4 chains of the
     blocked logistic GLM."""
     if w.n * w.p <= 1e6:
-        return min(w.K, 16)
+        return w.K
     return min(w.K, max(1, 200 // w.L))
 
 
@@ -109,13 +109,15 @@ def cpu_baseline(w, budget_s=15.0, numpy_budget_s=8.0):
     k_sub = baseline_folds(w)
     sub = W.fold_subset(w, 0, k_sub)
 
+    cap = w.n_iter                   # at most the whole run (warm-up included)
+
     def timed(step, budget):
         t0 = time.perf_counter()
         iters = 0
         while True:
             step()
             iters += 1
-            if time.perf_counter() - t0 > budget or iters >= 500:
+            if time.perf_counter() - t0 > budget or iters >= cap:
                 return iters, time.perf_counter() - t0
 
     try:
