@@ -156,15 +156,19 @@ def test_any_width_leapfrog_matches_oracle(dev, name, p, folds_):
     s.close()
 
 
-def test_two_models_at_an_odd_width(dev):
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+def test_two_models_at_an_odd_width(dev, shape):
     """p = 17: model B drops covariates 3, 9 and 16 (the last one); both
-    models in one bf16x3 launch match the oracle's separate evaluations."""
+    models in one bf16x3 launch, in every launch shape (the kernels read the
+    selection masks when they split theta), match the oracle's separate
+    evaluations."""
     w = _narrow("c4", 17, (0, 16))
     m = np.ones((2, w.p), dtype=np.uint8)
     m[1, [3, 9, 16]] = 0
     w2 = W.with_models(w, m)
     theta = _theta(w2, seed=4)
     s = binding.PCV.from_workload(w2, precision=W.PREC_BF16X3)
+    s.set_launch_config(256 * shape + 7)
     lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
     lp, g = lp.cpu().numpy(), g.cpu().numpy()
     KL = w.K * w.L
@@ -177,7 +181,8 @@ def test_two_models_at_an_odd_width(dev):
         g_o = model.grad_log_density(wm, th, roles, foc)
         rel_v = np.abs(lp[mi * KL:(mi + 1) * KL] - lp_o) / np.abs(lp_o)
         rel_g = _normwise(g[mi * KL:(mi + 1) * KL], g_o)
-        _say(f"[width models] model {mi}: logp rel max {rel_v.max():.2e}  grad normwise max {rel_g.max():.2e}")
+        _say(f"[width models] shape {shape} model {mi}: logp rel max {rel_v.max():.2e}  "
+             f"grad normwise max {rel_g.max():.2e}")
         assert rel_v.max() < 1e-5
         assert rel_g.max() < 5e-5
     s.close()
