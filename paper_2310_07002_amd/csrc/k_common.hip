@@ -133,9 +133,15 @@ __global__ __launch_bounds__(64 * accept_max_y<FAM>()) void k_accept(DevModel m,
   const int k = fold_of_chain(m, cc);
   // the hierarchical Gaussian's -n_train log sigma_y (prior_quad's extra term)
   if (FAM == FAM_HGAUSS && y == 0) pq -= m.ntrain[k] * m.q1[(m.p + 2) * m.C + cc];
-  const int beg = m.test_ptr[k], nt = m.test_ptr[k + 1] - beg;
-  lp = log_pred_rows<FAM>(m, m.q1, cc, beg + static_cast<int>(static_cast<int64_t>(nt) * y / Y),
-                          beg + static_cast<int>(static_cast<int64_t>(nt) * (y + 1) / Y));
+  // the proposal's log predictive: k_testlp's partial sums, or (folds with
+  // few test rows) this wave's contiguous share of the fold's test rows
+  if (m.lp_part) {
+    for (int g = y; g < m.lp_groups; g += Y) lp += m.lp_part[static_cast<int64_t>(g) * m.C + cc];
+  } else {
+    const int beg = m.test_ptr[k], nt = m.test_ptr[k + 1] - beg;
+    lp = log_pred_rows<FAM>(m, m.q1, cc, beg + static_cast<int>(static_cast<int64_t>(nt) * y / Y),
+                            beg + static_cast<int>(static_cast<int64_t>(nt) * (y + 1) / Y));
+  }
   red[0][y][lane] = v;
   red[1][y][lane] = pq;
   red[2][y][lane] = k1;
@@ -185,6 +191,44 @@ __global__ __launch_bounds__(64 * accept_max_y<FAM>()) void k_accept(DevModel m,
   }
   __syncthreads();
   if (y == 0 && valid) record_draw<FAM>(m, c, t, accepted, divergent, s_sel);
+}
+
+// Log predictive of the proposal q1 over each chain's test rows (eq cv-score's
+// log p(y_test | theta)), spread over the chip for k_accept: workgroup
+// (chain block, group g) with Y waves; wave w takes test slot a = g Y + w of
+// each lane's fold (one row: eta summed over the coefficients in order, then
+// the row's log density with its constant), and the waves' terms are added in
+// wave order into lp_part[g][c].
+template <int FAM, bool MASKED>
+__global__ __launch_bounds__(64 * WIDE_MAX_Y) void k_testlp(DevModel m) {
+  __shared__ double red[WIDE_MAX_Y][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, Y = blockDim.x >> 6;
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const bool valid = c < m.C;
+  const int64_t cc = valid ? c : m.C - 1;
+  const int k = fold_of_chain(m, cc);
+  const int beg = m.test_ptr[k], nt = m.test_ptr[k + 1] - beg;
+  const int a = static_cast<int>(blockIdx.y) * Y + w;
+  double s = 0.0;
+  if (a < nt) {
+    const int64_t i = m.test_rows[beg + a];
+    double e = eta_row_batched<MASKED>(m, m.q1, cc, i, MASKED ? mask_row(m, cc) : nullptr);
+    double is2 = m.inv_sigma2, lsy = 0.0;
+    if (hier_fam<FAM>())
+      e += m.q1[m.p * m.C + cc] + exp(m.q1[(m.p + 1) * m.C + cc]) * m.q1[(hier_z0(m) + m.group_of[i]) * m.C + cc];
+    if (FAM == FAM_HGAUSS) {
+      lsy = m.q1[(m.p + 2) * m.C + cc];
+      is2 = exp(-2.0 * lsy);
+    }
+    s = ell0_64<FAM>(m.y64[i], e, is2) + m.rowc[i] - lsy;
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && valid) {
+    double v = 0.0;
+    for (int u = 0; u < Y; ++u) v += red[u][lane];
+    m.lp_part[static_cast<int64_t>(blockIdx.y) * m.C + c] = v;
+  }
 }
 
 // Log predictive at q0 for every chain (initialisation and set_state).
@@ -502,6 +546,17 @@ __global__ void k_kick_drift(DevModel m) {
     }                                                                                            \
   } while (0)
 
+#define PCV_FAM_DISPATCH_M(fam, KERNEL, MB, grid, block, st, ...)                                  \
+  do {                                                                                           \
+    switch (fam) {                                                                               \
+      case FAM_GAUSS: hipLaunchKernelGGL((KERNEL<FAM_GAUSS, MB>), grid, block, 0, st, __VA_ARGS__); break; \
+      case FAM_LOGIT: hipLaunchKernelGGL((KERNEL<FAM_LOGIT, MB>), grid, block, 0, st, __VA_ARGS__); break; \
+      case FAM_POIS: hipLaunchKernelGGL((KERNEL<FAM_POIS, MB>), grid, block, 0, st, __VA_ARGS__); break;   \
+      case FAM_HIER: hipLaunchKernelGGL((KERNEL<FAM_HIER, MB>), grid, block, 0, st, __VA_ARGS__); break;   \
+      case FAM_HGAUSS: hipLaunchKernelGGL((KERNEL<FAM_HGAUSS, MB>), grid, block, 0, st, __VA_ARGS__); break; \
+    }                                                                                            \
+  } while (0)
+
 hipError_t launch_tick(const DevModel& m, hipStream_t st) {
   hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, st, m);
   return hipGetLastError();
@@ -538,6 +593,19 @@ hipError_t launch_momentum(const DevModel& m, int64_t t, hipStream_t st) {
 hipError_t launch_accept(const DevModel& m, const double* V, int ns, int64_t t, hipStream_t st) {
   const int Y = std::min(wide_waves(m.C), m.family == FAM_GAUSS ? accept_max_y<FAM_GAUSS>() : WIDE_MAX_Y);
   PCV_FAM_DISPATCH(m.family, k_accept, dim3(nblocks(m.C, 64)), dim3(64 * Y), st, m, V, ns, t);
+  return hipGetLastError();
+}
+// Waves per workgroup of k_testlp: one per test slot, up to WIDE_MAX_Y; the
+// groups cover the largest fold's test rows.
+int testlp_waves(int max_test_rows) { return std::max(1, std::min(WIDE_MAX_Y, max_test_rows)); }
+int testlp_groups(int max_test_rows) {
+  const int Y = testlp_waves(max_test_rows);
+  return std::max(1, (max_test_rows + Y - 1) / Y);
+}
+hipError_t launch_testlp(const DevModel& m, int max_test_rows, hipStream_t st) {
+  const dim3 grid(nblocks(m.C, 64), m.lp_groups), block(64 * testlp_waves(max_test_rows));
+  if (m.mmask) PCV_FAM_DISPATCH_M(m.family, k_testlp, true, grid, block, st, m);
+  else PCV_FAM_DISPATCH_M(m.family, k_testlp, false, grid, block, st, m);
   return hipGetLastError();
 }
 hipError_t launch_logpred(const DevModel& m, hipStream_t st) {

@@ -149,24 +149,29 @@ def test_two_models_on_matrix_cores_track_separate_runs(dev):
     captured transition graphs, against each model run alone (its columns
     zeroed, its global chain ids): the row-split count may differ between
     the runs, so positions agree to the bf16x3 tolerance wherever the
-    accept decisions agree, which is nearly everywhere."""
+    accept decisions agree, which is nearly everywhere; so do the
+    accepted states' test-row log predictives (each model's selection mask
+    applied when they are formed)."""
     w = dataclasses.replace(W.fold_subset(W.make("c4"), 0, 16), n_warmup=3)
     w2 = W.with_models(w, _masks(w.p, list(range(0, 64, 5))))
     s = binding.PCV.from_workload(w2, precision=W.PREC_BF16X3)
     s.step(6)
-    th, _, _ = s.get_state()
+    th, _, sv = s.get_state()
     acc = s.get_accumulators(w.n_blocks)["n_accept"]
     KL = w.K * w.L
     for mi in range(2):
         one = binding.PCV.from_workload(W.model_of(w2, mi), precision=W.PREC_BF16X3)
         one.step(6)
-        t1, _, _ = one.get_state()
+        t1, _, s1 = one.get_state()
         a1 = one.get_accumulators(w.n_blocks)["n_accept"]
         sl = slice(mi * KL, (mi + 1) * KL)
         same = acc[sl] == a1
         err = _normwise(th[sl], t1)
-        _say(f"[models] c4 model {mi}: same decisions {same.mean():.3f}, max err (same) {err[same].max():.2e}")
+        serr = np.abs(sv[sl] - s1) / np.abs(s1)
+        _say(f"[models] c4 model {mi}: same decisions {same.mean():.3f}, max err (same) {err[same].max():.2e}, "
+             f"log predictive {serr[same].max():.2e}")
         assert same.mean() > 0.95
         assert err[same].max() < 1e-4
+        assert serr[same].max() < 1e-4
         one.close()
     s.close()
