@@ -800,10 +800,13 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   ctx->test_ptr_host = test_ptr;
   for (int k = 0; k < K; ++k) ctx->max_test_rows = std::max(ctx->max_test_rows, test_ptr[k + 1] - test_ptr[k]);
   // The proposal's test-row log predictive gets a kernel of its own (spread
-  // over test rows as well as chains) when a chain's share is long enough to
-  // pay for the extra launch: measured, 40 x 64 and 200 x 10 (rows x
-  // coefficients) gain 3-8% of a transition, 5 x 4 loses 3%.
-  if (static_cast<int64_t>(ctx->max_test_rows) * p > 512) {
+  // over test rows as well as chains) when the accept kernel's workgroups
+  // (one per 64 chains) are fewer than the CUs and a chain's share is long
+  // enough to pay for the extra launch.  Measured per transition: 4000 and
+  // 800 chains with 40 x 64 and 200 x 10 (rows x coefficients) gain 3-8%;
+  // 8000 chains with 5 x 4 lose 3%; 40000 chains with 10 x 128 lose 0.1%
+  // (their accept kernel already fills the chip).
+  if (static_cast<int64_t>(ctx->max_test_rows) * p > 512 && (C + 63) / 64 < 256) {
     m.lp_groups = testlp_groups(ctx->max_test_rows);
     TRY(dalloc(ctx, &m.lp_part, static_cast<size_t>(m.lp_groups) * static_cast<size_t>(C)));
   }
