@@ -89,8 +89,9 @@ __global__ __launch_bounds__(64 * WIDE_MAX_Y) void k_momentum(DevModel m, int64_
 }
 
 // Metropolis test and accumulation.  Phase 1 (all waves): value partials,
-// prior, kinetic energy and the log predictive of the proposal q1 over a
-// contiguous share of the fold's test rows.  Phase 2 (wave 0): log pi(q1),
+// prior, kinetic energy and the log predictive of the proposal q1 (the
+// partial sums k_testlp wrote, or a contiguous share of the fold's test
+// rows evaluated here).  Phase 2 (wave 0): log pi(q1),
 // the test, logp0 and s0 (the proposal's log predictive when accepted).
 // Phase 3 (all waves): q0, g0 := q1, g1 for accepted chains.  Phase 4
 // (wave 0): accumulation, which reads the selected q0 for the scores.
