@@ -252,7 +252,7 @@ def main():
         tune["knob"] = ("waves per workgroup" if "fused" in kname else
                         ("256 x kernel shape (0: 16x16x32, 1: 32x32x16, 2: 32x32x16 free schedule, "
                          "3: 16x16x32 with 16 chains per wave) + row splits") if "mfma" in kname
-                        else "row splits")
+                        else "1024 x waves per workgroup + row splits")
         log(f"bench: autotune chose {tune['knob']} = {tune['config']} ({tune['ms']:.4f} ms) in {tune['seconds']:.2f} s")
     s.step(args.warmup)
     torch.cuda.synchronize()

@@ -401,6 +401,8 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
  *   tiles, and at design widths up to 64 a 16x16x32 kernel with 16 chains
  *   per wave whose registers fit two workgroups per CU) and the number of
  *   row splits per chain tile, around the analytic choice made at init;
+ * - row-split VALU path: waves per workgroup (2, 4 or 8) and row splits
+ *   around the analytic choice, scaled to keep the rows per wave;
  * - fused VALU path: waves per workgroup, each owning a range of rows.
  * Timing runs on a scratch copy of the current positions, so the chains are
  * untouched.  The fastest shape is kept, and the captured transition graph is
@@ -413,8 +415,10 @@ pcv_status pcv_get_accumulators(pcv_ctx ctx, double* Z, double* U, double* U2, d
  * 256 * shape + splits, shape 0 = 16x16x32 MFMAs with 32 chains per wave
  * (256 per workgroup), 1 = 32x32x16 MFMAs in program order, 2 = the same
  * scheduled freely by the compiler, 3 = 16x16x32 MFMAs with 16 chains per
- * wave (128 per workgroup; p <= 64 only); row-split VALU path: splits; fused
- * VALU path: waves); ms receives its mean kernel time (both optional).
+ * wave (128 per workgroup; p <= 64 only); row-split VALU path: 1024 *
+ * waves + splits, waves 1, 2, 4 or 8 (a bare split count below 1024 keeps
+ * the context's waves); fused VALU path: waves); ms receives its mean kernel
+ * time (both optional).
  * Synchronises.
  * Errors: PCV_ERR_UNSUPPORTED on the plain fp64 path; PCV_ERR_INVALID_ARG if
  * the cache cannot be written; PCV_ERR_DEVICE. */

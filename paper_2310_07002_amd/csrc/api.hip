@@ -113,7 +113,7 @@ struct pcv_ctx_s {
   uint64_t fold_fp = 0;       // of the fold set alone (model comparison)
   int split_cap = 0;                    // row splits the partial buffers hold
   int max_test_rows = 0;                // test rows of the largest fold (k_testlp's grid)
-  int wave_rows_cap = 0;                // row-split VALU: splits the wave_rows buffer holds
+  size_t wave_rows_cap = 0;             // row-split VALU: entries the wave_rows buffer holds
   double* uscr = nullptr;               // row-split VALU, hierarchical: [C] log tau of the partials
   std::vector<int32_t> group_of_host;   // row-split VALU, hierarchical: groups of the rows
   std::vector<int32_t> test_ptr_host;   // [K+1] test rows of each fold (CSR)
@@ -375,9 +375,22 @@ std::vector<int32_t> valu_partition(int64_t n, int W) { return valu_partition_ra
 
 void drop_graph(pcv_ctx ctx);
 
-// Largest row-split count: each wave keeps at least 8 rows.
-int valu_split_max(pcv_ctx ctx) {
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(512, ctx->m.n / (8 * ctx->W))));
+// Largest row-split count at W waves per workgroup: each wave keeps at least 8 rows.
+int valu_split_max_w(pcv_ctx ctx, int W) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(512, ctx->m.n / (8 * W))));
+}
+int valu_split_max(pcv_ctx ctx) { return valu_split_max_w(ctx, ctx->W); }
+
+// Row-split VALU launch shape as one autotuner config: VALU_CFG_WAVES * W +
+// splits, W = 1, 2, 4 or 8 waves per workgroup; a bare split count (below
+// VALU_CFG_WAVES) keeps the context's waves.
+constexpr int VALU_CFG_WAVES = 1024;
+int valu_cfg_waves(pcv_ctx ctx, int cfg) { return cfg >= VALU_CFG_WAVES ? cfg / VALU_CFG_WAVES : ctx->W; }
+bool valu_split_cfg_ok(pcv_ctx ctx, int cfg) {
+  const int W = valu_cfg_waves(ctx, cfg), ns = cfg % VALU_CFG_WAVES;
+  return cfg >= 1 && (W == 1 || W == 2 || W == 4 || W == 8) &&
+         valu_smem_bytes(ctx->fp64, W, ctx->m.family, ctx->m.n_groups, ctx->pb) <= 65536 && ns >= 1 &&
+         ns <= valu_split_max_w(ctx, W);
 }
 
 // Row-split VALU path: ns splits of the rows, W waves each (even
@@ -393,11 +406,11 @@ pcv_status apply_valu_splits(pcv_ctx ctx, int ns) {
     const std::vector<int32_t> part = valu_partition_range(n * sp / ns, n * (sp + 1) / ns, W);
     wr.insert(wr.end(), part.begin(), part.end());
   }
-  if (ns > ctx->wave_rows_cap) {
+  if (wr.size() > ctx->wave_rows_cap) {   // ns x (W + 1) row bounds
     int32_t* d;
     TRY(dalloc(ctx, &d, wr.size()));
     ctx->wave_rows = d;
-    ctx->wave_rows_cap = ns;
+    ctx->wave_rows_cap = wr.size();
   }
   CK(hipMemcpy(ctx->wave_rows, wr.data(), sizeof(int32_t) * wr.size(), hipMemcpyHostToDevice));
   m.wave_rows = ctx->wave_rows;
@@ -437,6 +450,11 @@ pcv_status apply_valu_splits(pcv_ctx ctx, int ns) {
   ctx->n_splits = ns;
   drop_graph(ctx);
   return PCV_OK;
+}
+pcv_status apply_valu_split_cfg(pcv_ctx ctx, int cfg) {
+  if (!valu_split_cfg_ok(ctx, cfg)) return fail(ctx, PCV_ERR_INVALID_ARG, "invalid row-split launch configuration");
+  ctx->W = valu_cfg_waves(ctx, cfg);
+  return apply_valu_splits(ctx, cfg % VALU_CFG_WAVES);
 }
 
 
@@ -1941,11 +1959,11 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   for (const TuneEntry& e : cache) {
     if (e.key != key) continue;
     const bool valid = ctx->path == PATH_MFMA        ? mfma_cfg_ok(ctx, e.cfg)
-                       : ctx->path == PATH_VALU_SPLIT ? (e.cfg >= 1 && e.cfg <= valu_split_max(ctx))
+                       : ctx->path == PATH_VALU_SPLIT ? valu_split_cfg_ok(ctx, e.cfg)
                                                       : waves_ok(ctx, e.cfg);
     if (!valid) break;   // stale entry: tune again
     if (ctx->path == PATH_MFMA) TRY(apply_mfma_cfg(ctx, e.cfg));
-    else if (ctx->path == PATH_VALU_SPLIT) TRY(apply_valu_splits(ctx, e.cfg));
+    else if (ctx->path == PATH_VALU_SPLIT) TRY(apply_valu_split_cfg(ctx, e.cfg));
     else TRY(apply_waves(ctx, e.cfg));
     if (config) *config = e.cfg;
     if (ms) *ms = e.ms;
@@ -1953,10 +1971,15 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   }
   std::vector<int> cand;
   if (ctx->path == PATH_VALU_SPLIT) {
-    const int ns0 = ctx->n_splits;
-    for (int ns : {ns0 / 2, (3 * ns0) / 4, ns0, (3 * ns0) / 2, 2 * ns0})
-      if (ns >= 1 && ns <= valu_split_max(ctx) && std::find(cand.begin(), cand.end(), ns) == cand.end())
-        cand.push_back(ns);
+    // waves per workgroup (2, 4 or 8) and split counts around the analytic
+    // choice, scaled to keep the rows per wave: config = VALU_CFG_WAVES * W + splits
+    const int ns0 = ctx->n_splits, W0 = ctx->W;
+    for (int W : {2, 4, 8})
+      for (int f : {2, 3, 4, 6, 8}) {   // ns0 x f / 4
+        const int ns = std::max(1, ns0 * f * W0 / (4 * W));
+        const int cfg = VALU_CFG_WAVES * W + ns;
+        if (valu_split_cfg_ok(ctx, cfg) && std::find(cand.begin(), cand.end(), cfg) == cand.end()) cand.push_back(cfg);
+      }
   } else if (ctx->path == PATH_MFMA) {
     // every MFMA launch shape the width allows, each with row-split counts
     // around the analytic choice: config = MFMA_CFG_SHAPE * shape + splits
@@ -1986,7 +2009,7 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
     for (size_t ci = 0; ci < cand.size(); ++ci) {
       const int c = cand[ci];
       s = ctx->path == PATH_MFMA ? apply_mfma_cfg(ctx, c) : ctx->path == PATH_VALU ? apply_waves(ctx, c)
-                                                                                   : apply_valu_splits(ctx, c);
+                                                                                   : apply_valu_split_cfg(ctx, c);
       double t = 0.0;
       if (s == PCV_OK) s = time_hot(ctx, reps, &t);
       if (s != PCV_OK) break;
@@ -2004,7 +2027,7 @@ pcv_status pcv_autotune(pcv_ctx ctx, const char* cache_path, int32_t* config, do
   if (s != PCV_OK) return s;
   TRY(ctx->path == PATH_MFMA   ? apply_mfma_cfg(ctx, best)
       : ctx->path == PATH_VALU ? apply_waves(ctx, best)
-                               : apply_valu_splits(ctx, best));
+                               : apply_valu_split_cfg(ctx, best));
   if (config) *config = best;
   if (ms) *ms = best_ms;
   if (cache_path) {
@@ -2026,11 +2049,11 @@ pcv_status pcv_set_launch_config(pcv_ctx ctx, int32_t config) {
   if (!usable(ctx)) return PCV_ERR_STATE;
   if (ctx->path == PATH_UNFUSED) return fail(ctx, PCV_ERR_UNSUPPORTED, "the plain fp64 path has no launch shape");
   const bool valid = ctx->path == PATH_MFMA        ? mfma_cfg_ok(ctx, config)
-                     : ctx->path == PATH_VALU_SPLIT ? (config >= 1 && config <= valu_split_max(ctx))
+                     : ctx->path == PATH_VALU_SPLIT ? valu_split_cfg_ok(ctx, config)
                                                     : waves_ok(ctx, config);
   if (!valid) return fail(ctx, PCV_ERR_INVALID_ARG, "launch configuration out of range for this context");
   if (ctx->path == PATH_MFMA) TRY(apply_mfma_cfg(ctx, config));
-  else if (ctx->path == PATH_VALU_SPLIT) TRY(apply_valu_splits(ctx, config));
+  else if (ctx->path == PATH_VALU_SPLIT) TRY(apply_valu_split_cfg(ctx, config));
   else TRY(apply_waves(ctx, config));
   return PCV_OK;
 }
@@ -2040,7 +2063,7 @@ pcv_status pcv_get_launch_config(pcv_ctx ctx, int32_t* config) {
   if (!config) return fail(ctx, PCV_ERR_INVALID_ARG, "null output");
   if (ctx->path == PATH_UNFUSED) return fail(ctx, PCV_ERR_UNSUPPORTED, "the plain fp64 path has no launch shape");
   *config = ctx->path == PATH_MFMA ? MFMA_CFG_SHAPE * ctx->mshape + ctx->n_splits
-            : ctx->path == PATH_VALU_SPLIT ? ctx->n_splits : ctx->W;
+            : ctx->path == PATH_VALU_SPLIT ? VALU_CFG_WAVES * ctx->W + ctx->n_splits : ctx->W;
   return PCV_OK;
 }
 

@@ -202,6 +202,36 @@ def test_leapfrog_every_tile_shape_matches_oracle(dev, shape, label, make_w, pre
     s.close()
 
 
+@pytest.mark.parametrize("name,folds_,prec,tol", [("c2", (0, 10), "fp32", 2e-6), ("c3", (0, 40), "fp64", 1e-12)])
+def test_row_split_waves_and_splits_match_oracle(dev, name, folds_, prec, tol):
+    """The row-split VALU path at several launch shapes, 1024 x waves per
+    workgroup + row splits (the hierarchical family and interval folds):
+    value and gradient against the oracle at each; shapes the path cannot
+    run are refused and leave the context as it was."""
+    w = W.fold_subset(W.make(name), *folds_)
+    theta = _theta_near_init(w, seed=6)
+    lp_o, g_o = _oracle_eval(w, theta)
+    s = binding.PCV.from_workload(w, precision=PREC[prec])
+    for W_, ns in ((1, 3), (2, 17), (4, 1), (8, 9), (8, 40)):
+        cfg = 1024 * W_ + ns
+        s.set_launch_config(cfg)
+        assert s.launch_config() == cfg
+        lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+        rel_v = np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)
+        rel_g = _normwise(g.cpu().numpy(), g_o)
+        _say(f"[row-split shape] {name} {prec} waves {W_} splits {ns}: logp rel max {rel_v.max():.2e}  "
+             f"grad normwise max {rel_g.max():.2e}")
+        assert rel_v.max() < tol and rel_g.max() < tol
+    for bad in (1024 * 3 + 4, 1024 * 16 + 4, 1024 * 4 + 0, 1024 * 8 + 1000):   # waves 3, 16; no split; too many
+        with pytest.raises(binding.PcvError):
+            s.set_launch_config(bad)
+    assert s.launch_config() == 1024 * 8 + 40
+    s.step(2)
+    th, lp2, _ = s.get_state()
+    assert np.isfinite(th).all() and np.isfinite(lp2).all()
+    s.close()
+
+
 @pytest.mark.parametrize("prec,tol_v,tol_g", [("bf16x3", 1e-5, 5e-5), ("bf16x5", 1e-5, 1e-5)])
 def test_interval_folds_on_matrix_cores(dev, prec, tol_v, tol_g):
     """hv-block style folds (test block plus a buffer of h rows each side,
