@@ -453,8 +453,11 @@ pcv_status apply_valu_splits(pcv_ctx ctx, int ns) {
 }
 pcv_status apply_valu_split_cfg(pcv_ctx ctx, int cfg) {
   if (!valu_split_cfg_ok(ctx, cfg)) return fail(ctx, PCV_ERR_INVALID_ARG, "invalid row-split launch configuration");
-  ctx->W = valu_cfg_waves(ctx, cfg);
-  return apply_valu_splits(ctx, cfg % VALU_CFG_WAVES);
+  const int W0 = ctx->W;
+  ctx->W = valu_cfg_waves(ctx, cfg);   // the row partition is built for the new waves
+  const pcv_status s = apply_valu_splits(ctx, cfg % VALU_CFG_WAVES);
+  if (s != PCV_OK) ctx->W = W0;
+  return s;
 }
 
 
