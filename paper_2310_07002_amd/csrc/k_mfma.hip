@@ -84,8 +84,15 @@ __device__ __forceinline__ float mf_resid(float y, float e2, float is2) {
 
 // Value launches need the residual and the log-likelihood of the same
 // element; one exponential serves both (logistic: t = e^{-|eta|} gives
-// sigma(eta) = (eta >= 0 ? 1 : t) / (1 + t) and log1p(t) from the same
-// 1 + t; Poisson: the mean; Gaussian: the difference y - eta).
+// sigma(eta) = (eta >= 0 ? 1 : t) / (1 + t) and log(1 + t) from the same
+// 1 + t; Poisson: the mean; Gaussian: the difference y - eta).  The
+// logistic l0 is returned in base-2 units (l0 / ln 2: the logarithm is the
+// hardware's log2 and e2 = eta log2 e already); mf_ell0_scale gives the
+// factor the launch applies to its per-chain sums.  log2 of the rounded
+// 1 + t loses at most one ulp of 1 (below 2e-7) where t is tiny, against
+// terms of order 1.
+template <int FAM>
+__host__ __device__ constexpr double mf_ell0_scale() { return FAM == FAM_LOGIT ? 0.6931471805599453 : 1.0; }
 template <int FAM>
 __device__ __forceinline__ void mf_resid_ell0(float y, float e2, float is2, float& r, float& l0) {
   if (FAM == FAM_GAUSS) {
@@ -100,8 +107,7 @@ __device__ __forceinline__ void mf_resid_ell0(float y, float e2, float is2, floa
     const float t = __builtin_amdgcn_exp2f(-fabsf(e2));    // e^{-|eta|} in (0, 1]
     const float q = 1.0f + t;
     r = y - (e2 >= 0.0f ? 1.0f : t) * __builtin_amdgcn_rcpf(q);
-    const float l1p = t > 1e-4f ? __builtin_amdgcn_logf(q) * LN2_F : t * (1.0f - 0.5f * t);
-    l0 = (y * e2 - fmaxf(e2, 0.0f)) * LN2_F - l1p;
+    l0 = y * e2 - fmaxf(e2, 0.0f) - __builtin_amdgcn_logf(q);   // base 2
   }
 }
 
@@ -471,7 +477,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(CB == 1 ? 4
       double v = vacc[cb];
       v += __shfl_xor(v, 16);
       v += __shfl_xor(v, 32);
-      if (lane < 16 && c < m.C) a.Vpart[static_cast<int64_t>(sp) * m.C + c] = v;
+      if (lane < 16 && c < m.C) a.Vpart[static_cast<int64_t>(sp) * m.C + c] = v * mf_ell0_scale<FAM>();
     }
   }
 }
@@ -797,7 +803,7 @@ __global__ __launch_bounds__(512) void k_mfma32(MfmaArgs a) {
   if (VALUE) {
     double v = vacc;
     v += __shfl_xor(v, 32);
-    if (lane < 32 && cvalid) a.Vpart[static_cast<int64_t>(sp) * m.C + cidx] = v;
+    if (lane < 32 && cvalid) a.Vpart[static_cast<int64_t>(sp) * m.C + cidx] = v * mf_ell0_scale<FAM>();
   }
 }
 
