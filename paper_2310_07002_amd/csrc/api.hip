@@ -827,7 +827,8 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
   // 800 chains with 40 x 64 and 200 x 10 (rows x coefficients) gain 3-8%;
   // 8000 chains with 5 x 4 lose 3%; 40000 chains with 10 x 128 lose 0.1%
   // (their accept kernel already fills the chip).
-  if (static_cast<int64_t>(ctx->max_test_rows) * p > 512 && (C + 63) / 64 < 256) {
+  // (k_testlp stages a block's coefficients in LDS: designs of up to 128.)
+  if (static_cast<int64_t>(ctx->max_test_rows) * p > 512 && (C + 63) / 64 < 256 && p <= 128) {
     m.lp_groups = testlp_groups(ctx->max_test_rows);
     TRY(dalloc(ctx, &m.lp_part, static_cast<size_t>(m.lp_groups) * static_cast<size_t>(C)));
   }

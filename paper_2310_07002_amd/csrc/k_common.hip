@@ -199,12 +199,30 @@ __global__ __launch_bounds__(64 * accept_max_y<FAM>()) void k_accept(DevModel m,
 // (chain block, group g) with Y waves; wave w takes test slot a = g Y + w of
 // each lane's fold (one row: eta summed over the coefficients in order, then
 // the row's log density with its constant), and the waves' terms are added in
-// wave order into lp_part[g][c].
+// wave order into lp_part[g][c].  The block's coefficients (zero where a
+// nested model drops one) are staged in LDS once, so the Y waves read them
+// there instead of each fetching all of them again from L2.
+constexpr int TESTLP_MAX_P = 128;
 template <int FAM, bool MASKED>
 __global__ __launch_bounds__(64 * WIDE_MAX_Y) void k_testlp(DevModel m) {
+  __shared__ double sq[TESTLP_MAX_P * 64];   // [j][lane]
   __shared__ double red[WIDE_MAX_Y][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, Y = blockDim.x >> 6;
-  const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + lane;
+  const int64_t cbase = static_cast<int64_t>(blockIdx.x) * 64;
+  const int p = static_cast<int>(m.p);
+  for (int t = threadIdx.x; t < p * 64; t += blockDim.x) {
+    const int j = t >> 6, l = t & 63;
+    const int64_t cl = cbase + l < m.C ? cbase + l : m.C - 1;
+    const double v = m.q1[static_cast<int64_t>(j) * m.C + cl];
+    if (MASKED) {
+      const uint8_t keep = mask_row(m, cl)[j];
+      sq[t] = keep ? v : 0.0;
+    } else {
+      sq[t] = v;
+    }
+  }
+  __syncthreads();
+  const int64_t c = cbase + lane;
   const bool valid = c < m.C;
   const int64_t cc = valid ? c : m.C - 1;
   const int k = fold_of_chain(m, cc);
@@ -213,7 +231,17 @@ __global__ __launch_bounds__(64 * WIDE_MAX_Y) void k_testlp(DevModel m) {
   double s = 0.0;
   if (a < nt) {
     const int64_t i = m.test_rows[beg + a];
-    double e = eta_row_batched<MASKED>(m, m.q1, cc, i, MASKED ? mask_row(m, cc) : nullptr);
+    const double* x = m.X64 + i * m.p;
+    double e = 0.0;
+    constexpr int LB = 16;
+    for (int j0 = 0; j0 < p; j0 += LB) {
+      double xv[LB];
+#pragma unroll
+      for (int v = 0; v < LB; ++v) xv[v] = x[j0 + v < p ? j0 + v : j0];
+#pragma unroll
+      for (int v = 0; v < LB; ++v)
+        if (j0 + v < p) e += xv[v] * sq[(j0 + v) * 64 + lane];
+    }
     double is2 = m.inv_sigma2, lsy = 0.0;
     if (hier_fam<FAM>())
       e += m.q1[m.p * m.C + cc] + exp(m.q1[(m.p + 1) * m.C + cc]) * m.q1[(hier_z0(m) + m.group_of[i]) * m.C + cc];

@@ -337,37 +337,6 @@ __device__ double log_pred_rows_m(const DevModel& m, const double* q, int64_t c,
   }
   return s;
 }
-// eta of row i for chain c at position q ([d][C]) in fp64, the coefficients
-// summed in order; the loads of 16 coefficients at a time are issued together
-// (clamped indices, the selection after).  mrow: the chain's covariate mask
-// (MASKED only).
-template <bool MASKED>
-__device__ __forceinline__ double eta_row_batched(const DevModel& m, const double* q, int64_t c, int64_t i,
-                                                  const uint8_t* mrow) {
-  const double* x = m.X64 + i * m.p;
-  constexpr int LB = 16;
-  double e = 0.0;
-  for (int64_t j0 = 0; j0 < m.p; j0 += LB) {
-    double xv[LB], qv[LB];
-#pragma unroll
-    for (int v = 0; v < LB; ++v) {
-      const int64_t j = j0 + v < m.p ? j0 + v : j0;
-      xv[v] = x[j];
-      const double t = q[j * m.C + c];
-      if (MASKED) {
-        const uint8_t keep = mrow[j];
-        qv[v] = keep ? t : 0.0;
-      } else {
-        qv[v] = t;
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < LB; ++v)
-      if (j0 + v < m.p) e += xv[v] * qv[v];
-  }
-  return e;
-}
-
 template <int FAM>
 __device__ double log_pred_rows(const DevModel& m, const double* q, int64_t c, int a0, int a1) {
   return m.mmask ? log_pred_rows_m<FAM, true>(m, q, c, a0, a1) : log_pred_rows_m<FAM, false>(m, q, c, a0, a1);

@@ -1,6 +1,7 @@
 """Host-side logic of bench.py, CPU only: the traffic look-up keyed to the
 kernel sources and the launch shape, the bounded CPU-baseline sample, and the
 one-GPU guard (no device is touched)."""
+import hashlib
 import json
 import os
 import shutil
@@ -22,25 +23,40 @@ def _copy_tree(tmp_path):
     return tmp_path
 
 
+def _source_hash(root, kernel):
+    h = hashlib.sha256()
+    for f in ("k_mfma.hip" if kernel == "k_mfma" else "k_valu.hip", "pcv_internal.h"):
+        with open(os.path.join(root, "paper_2310_07002_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 @pytest.mark.parametrize("name,prec,kernel", [("c5", "bf16x3", "k_mfma"), ("c4", "bf16x3", "k_mfma"),
                                               ("c3", "fp64", "k_valu_part"), ("c2", "fp32", "k_valu_part")])
 def test_traffic_follows_sources_and_launch_shape(tmp_path, monkeypatch, name, prec, kernel):
+    """A counter summary keyed to the current sources gives its bytes at its
+    own shape and at the other shapes it holds, nothing at a shape it does
+    not hold, and nothing once the kernel's sources change."""
     w = W.make(name)
     root = _copy_tree(tmp_path)
     monkeypatch.setattr(bench, "ROOT", str(root))
-    with open(root / "profiles" / f"traffic_{w.name}_{prec}.json") as f:
-        t = json.load(f)
-    cfg = t["launch_config"]
-    # the committed summary matches the committed sources at its own shape and the others it holds
-    assert bench.traffic_from_profiles(w, prec, kernel, cfg) == t["bytes_per_launch"]
-    for other, v in t.get("other_launch_configs", {}).items():
-        assert bench.traffic_from_profiles(w, prec, kernel, int(other)) == v["bytes_per_launch"]
-    # a shape it holds no counters for gives no traffic
+    t = {"kernel_source_sha256_16": _source_hash(root, kernel), "launch_config": 13, "bytes_per_launch": 1.5e9,
+         "other_launch_configs": {"11": {"bytes_per_launch": 1.3e9}}}
+    with open(root / "profiles" / f"traffic_{w.name}_{prec}.json", "w") as f:
+        json.dump(t, f)
+    assert bench.traffic_from_profiles(w, prec, kernel, 13) == 1.5e9
+    assert bench.traffic_from_profiles(w, prec, kernel, 11) == 1.3e9
     assert bench.traffic_from_profiles(w, prec, kernel, 99999) is None
-    # any change to the kernel's sources or the shared header voids it
     src = root / "paper_2310_07002_amd" / "csrc" / ("k_mfma.hip" if kernel == "k_mfma" else "k_valu.hip")
     src.write_text(src.read_text() + "\n// edited\n")
-    assert bench.traffic_from_profiles(w, prec, kernel, cfg) is None
+    assert bench.traffic_from_profiles(w, prec, kernel, 13) is None
+    hdr = root / "paper_2310_07002_amd" / "csrc" / "pcv_internal.h"
+    t["kernel_source_sha256_16"] = _source_hash(root, kernel)
+    with open(root / "profiles" / f"traffic_{w.name}_{prec}.json", "w") as f:
+        json.dump(t, f)
+    assert bench.traffic_from_profiles(w, prec, kernel, 13) == 1.5e9
+    hdr.write_text(hdr.read_text() + "\n// edited\n")
+    assert bench.traffic_from_profiles(w, prec, kernel, 13) is None
 
 
 def test_traffic_missing_summary_is_none(tmp_path, monkeypatch):
