@@ -19,7 +19,7 @@ hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int
 size_t valu_smem_bytes(bool fp64, int W, int family, int n_groups, int pb);
 int valu_part_occupancy(bool fp64, int family, int pb, int W, size_t smem);
 hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int ns, double* Gpart,
-                            double* Vpart, double* uscr, bool value, hipStream_t st);
+                            double* Vpart, double* uscr, bool value, bool series, hipStream_t st);
 hipError_t launch_valu_finish(const DevModel& m, const double* Gpart, const double* uscr, int ns, int mode,
                               hipStream_t st);
 int valu_pb(int64_t p, bool fp64);
@@ -67,6 +67,7 @@ struct pcv_ctx_s {
   int prec = 0, path = 0;
   bool fp64 = true;
   int pb = 0, W = 1;
+  bool series = false;   // X is the lag matrix of y (row-split VALU path)
   hipStream_t st = nullptr;
   int64_t t = 0;
   std::vector<void*> allocs;
@@ -220,7 +221,7 @@ pcv_status split_partials(pcv_ctx ctx, bool value) {
     if (ctx->ev_used + 2 > 4096) timing_collect(ctx);
     timing_begin(ctx);
     CK(launch_valu_part(m, ctx->Xv, ctx->fp64, ctx->pb, ctx->W, ctx->n_splits, ctx->Gpart64, ctx->Vpart, ctx->uscr,
-                        value, ctx->st));
+                        value, ctx->series, ctx->st));
     timing_end(ctx);
     return PCV_OK;
   }
@@ -924,6 +925,17 @@ static pcv_status init_impl(pcv_ctx ctx, const pcv_model* md, const double* X, c
       TRY(upload(ctx, &xd, xv.data(), xv.size()));
       ctx->Xv = xd;
       m.X32 = xd;
+    }
+    // Autoregressive designs: every row after the first holds the previous
+    // row's response followed by the previous row's first p - 1 coefficients
+    // (exact equality), so the row-split kernel slides them in registers.
+    if (ctx->path == PATH_VALU_SPLIT && !hier && pb == p && n >= 2) {
+      bool lag = true;
+      for (int64_t i = 1; i < n && lag; ++i) {
+        lag = X[i * p] == y[i - 1];
+        for (int64_t j = 1; j < p && lag; ++j) lag = X[i * p + j] == X[(i - 1) * p + j - 1];
+      }
+      ctx->series = lag;
     }
     if (ctx->path == PATH_VALU_SPLIT) {
       // W waves per workgroup, row splits so that (chain blocks x splits)

@@ -26,6 +26,7 @@ struct ValuArgs {
   double* Vpart;
   int value;
   double* uscr;   // hierarchical: [C] log tau at the evaluation point (split 0 writes it)
+  int series;     // MODE_PART, GLM families: X holds the lags of y (see grad_eval)
 };
 
 template <typename T>
@@ -81,7 +82,7 @@ template <typename T, int FAM, int PB, bool VALUE>
 __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict__ Xv, int lane, int wave,
                                           int W, int64_t cc, int k, int elo, int ehi, T (&G)[PB],
                                           double& val, double& qsum, char* smem, bool want_value = true,
-                                          const int32_t* wave_rows = nullptr) {
+                                          const int32_t* wave_rows = nullptr, bool series = false) {
   constexpr int JC = valu_jc<T, PB>();
   T* red = reinterpret_cast<T*>(smem);                                      // [W][JC][64]
   double* vred = reinterpret_cast<double*>(smem + sizeof(T) * W * JC * 64);  // [W][64]
@@ -166,6 +167,29 @@ __device__ __forceinline__ void grad_eval(const DevModel& m, const T* __restrict
     // GLM rows: four rows per trip puts their scalar loads under one wait.
     // The hierarchical row carries a group-change branch and gains nothing.
     constexpr int RU = hier_fam<FAM>() ? 1 : 4;
+    if constexpr (!hier_fam<FAM>()) {
+      // Autoregressive design (p = PB lags of the response): row i + 1's
+      // coefficients are row i's response followed by row i's first PB - 1
+      // coefficients, so after the first row of the range only responses
+      // are loaded and the coefficients slide through registers.  The host
+      // checks the identity exactly; the values and their order are those
+      // of the general loop below.
+      if (series) {
+        if (ra >= rb) return;
+        T xv[PB];
+#pragma unroll
+        for (int j = 0; j < PB; ++j) xv[j] = Xv[ra * PB + j];
+#pragma unroll RU
+        for (int64_t i = ra; i < rb; ++i) {
+          const T y = ValuY<T>::get(m, i);
+          row(fold_kind, i, xv, y, 0, FKR == PCV_FOLDS_INDEX ? m.fold_index[i] : 0);
+#pragma unroll
+          for (int j = PB - 1; j > 0; --j) xv[j] = xv[j - 1];
+          xv[0] = y;
+        }
+        return;
+      }
+    }
 #pragma unroll RU
     for (int64_t i = ra; i < rb; ++i) {
       const T* xr = Xv + i * PB;
@@ -402,8 +426,9 @@ __global__ __launch_bounds__(VALU_MAX_THREADS) void k_valu_part(ValuArgs a) {
   VALU_PROLOGUE
   const int sp = blockIdx.y;
   const int32_t* wr = m.wave_rows + static_cast<int64_t>(sp) * (W + 1);
-  if (a.value) grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem, true, wr);
-  else grad_eval<T, FAM, PB, false>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem, false, wr);
+  const bool series = a.series != 0;
+  if (a.value) grad_eval<T, FAM, PB, true>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem, true, wr, series);
+  else grad_eval<T, FAM, PB, false>(m, Xv, lane, wave, W, cc, k, elo, ehi, G, val, qsum, smem, false, wr, series);
   if (lead) {
     constexpr int JC = valu_jc<T, PB>();
     T* zt = reinterpret_cast<T*>(smem + sizeof(T) * W * JC * 64 + sizeof(double) * W * 64);
@@ -613,7 +638,7 @@ hipError_t launch_valu(const DevModel& m, const void* Xv, bool fp64, int pb, int
 }
 
 hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb, int W, int ns, double* Gpart,
-                            double* Vpart, double* uscr, bool value, hipStream_t st) {
+                            double* Vpart, double* uscr, bool value, bool series, hipStream_t st) {
   ValuArgs a{};
   a.m = m;
   a.Xv = Xv;
@@ -622,6 +647,7 @@ hipError_t launch_valu_part(const DevModel& m, const void* Xv, bool fp64, int pb
   a.Vpart = Vpart;
   a.uscr = uscr;
   a.value = value ? 1 : 0;
+  a.series = series && !hier_family(m.family) ? 1 : 0;
   const int nblk = static_cast<int>((m.C + 63) / 64);
   const size_t smem = valu_smem_bytes(fp64, W, m.family, m.n_groups, pb);
   if (fp64) {

@@ -309,6 +309,38 @@ def test_interval_fold_forms(dev, path):
         np.testing.assert_allclose(sv, run.state.s, rtol=1e-10, atol=1e-12)
 
 
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_FP32])
+@pytest.mark.parametrize("lagged", [True, False])
+def test_autoregressive_rows_on_split_path(dev, prec, lagged):
+    """The AR(4) design (every row's lags are the previous row's response and
+    lags, which the row-split kernel slides in registers) with index-coded
+    contiguous folds, and the same design one ulp off that identity (the
+    general row loop): value and gradient against the oracle, and in fp64
+    three whole transitions replayed."""
+    w = W.fold_subset(W.make("c3"), 296, 336)
+    X = w.X.copy()
+    if not lagged:
+        X[700, 2] = np.nextafter(X[700, 2], np.inf)
+    fi = (np.arange(w.n) * w.K // w.n).astype(np.int32)
+    w = dataclasses.replace(w, X=X, fold_kind=W.FOLDS_INDEX, fold_index=fi, intervals=None, n_warmup=2)
+    _say(f"[autoregressive rows] lagged={lagged} prec={prec} n={w.n} C={w.C}")
+    theta = _theta_near_init(w, seed=8)
+    lp_o, g_o = _oracle_eval(w, theta)
+    s = binding.PCV.from_workload(w, precision=prec)
+    lp, g = s.logdensity_grad(torch.tensor(theta, device=dev))
+    rel_v = np.abs(lp.cpu().numpy() - lp_o) / np.abs(lp_o)
+    rel_g = _normwise(g.cpu().numpy(), g_o)
+    _say(f"    logp rel max {rel_v.max():.2e}  grad normwise max {rel_g.max():.2e}")
+    tol = 1e-12 if prec == W.PREC_FP64 else 1e-5
+    assert rel_v.max() < tol
+    assert rel_g.max() < tol
+    if prec == W.PREC_FP64:
+        run, s2 = _replay(w, 3, dev, prec=prec)
+        th, _, sv = s2.get_state()
+        np.testing.assert_allclose(th, run.state.q, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(sv, run.state.s, rtol=1e-10, atol=1e-12)
+
+
 def test_dense_fold_encoding_matches_index(dev):
     w = W.fold_subset(W.make("c1"), 0, 30)
     wd = W.with_dense_roles(w)
